@@ -1,0 +1,174 @@
+/*
+ * covest.h -- C ABI of libcovest, the sliding-window estimated covariance
+ * matrix on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Green, David, Galperin, Birk, "Efficient Parallel Computation
+ * of the Estimated Covariance Matrix", Sec. 2.2, eqs. 2.1-2.2): for a complex
+ * N x M input A and a P x Q window, every window position (p, q) with
+ * 0 <= p <= N-P, 0 <= q <= M-Q gives the column stack V^{p,q}, whose entry
+ * k = i + P*j is A[p+i][q+j].  The estimated covariance matrix is
+ *
+ *     R = (1/K) * sum_{p,q} V^{p,q} (V^{p,q})^H,     K = (N-P+1)(M-Q+1),
+ *
+ * a PQ x PQ Hermitian positive semi-definite matrix; entry (k1, k2) is
+ * (1/K) sum_{p,q} A[p+i1][q+j1] * conj(A[p+i2][q+j2]).
+ *
+ * Conventions shared by every call:
+ *   - A is complex64 (interleaved float re, im), row-major, A[n*lda + m] with
+ *     n the row (0 <= n < N) and lda >= M (lda = M for the plain calls).
+ *   - R is PQ x PQ row-major.  Its element type is complex128 (interleaved
+ *     double) when opts->prec == COVEST_PREC_FP64 and complex64 otherwise.
+ *   - All pointers named A, R, dR, dA, ws are DEVICE pointers on the current
+ *     HIP device, owned by the caller.  The library never frees caller memory.
+ *   - All device work is enqueued on `stream` (0 = the null stream) and is
+ *     stream-ordered: no call synchronises the host unless COVEST_SYNC=1 is set
+ *     in the environment, which makes every call wait and check for errors.
+ *   - R must not alias A; dA must not alias A or dR.
+ *   - Every call returns a covest_status; no C++ exception crosses the ABI.
+ *     On a non-OK status covest_last_error() describes the problem.
+ *   - Calls on different streams may run concurrently.
+ */
+#ifndef COVEST_H
+#define COVEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COVEST_VERSION 1
+
+typedef enum {
+    COVEST_OK = 0,
+    COVEST_ERR_INVALID_ARG = -1,   /* null pointer, bad enum, bad leading dimension   */
+    COVEST_ERR_SHAPE = -2,         /* P < 1, Q < 1, P > N, Q > M, or size overflow     */
+    COVEST_ERR_WORKSPACE = -3,     /* ws_bytes below covest_workspace_size()          */
+    COVEST_ERR_HIP = -4,           /* a HIP runtime call failed                        */
+    COVEST_ERR_UNSUPPORTED = -5,   /* form/precision/shape combination not provided   */
+    COVEST_ERR_PLAN_MISMATCH = -6  /* a batched plan was used on another device/state */
+} covest_status;
+
+/* Which kernel family computes R. */
+typedef enum {
+    COVEST_FORM_AUTO = 0,          /* recurrence (the faster form for every size)          */
+    COVEST_FORM_RECURRENCE = 1,    /* diagonal-segment recurrence, FP64 sums (Sec. 3)      */
+    COVEST_FORM_HANKEL_MFMA = 2    /* R = X X^H / K as a dense product on matrix cores     */
+} covest_form;
+
+typedef enum {
+    COVEST_PREC_FP64 = 0,   /* recurrence: FP64 products and sums, complex128 R            */
+    COVEST_PREC_FP32 = 1,   /* recurrence: FP64 sums rounded to complex64 R;
+                               Hankel: FP32 matrix-core products, FP64 split-K reduction   */
+    COVEST_PREC_BF16X3 = 2, /* Hankel: A split into bf16 hi + lo, hi*hi + hi*lo + lo*hi     */
+    COVEST_PREC_FP16X3 = 3, /* Hankel: same with fp16 planes (lo plane scaled by 2^11)      */
+    COVEST_PREC_BF16 = 4,   /* Hankel: plain bf16 inputs, FP32 accumulation                 */
+    COVEST_PREC_FP16 = 5    /* Hankel: plain fp16 inputs, FP32 accumulation                 */
+} covest_precision;
+
+typedef enum {
+    COVEST_FILL_FULL = 0,   /* whole R; the lower triangle is the exact conjugate mirror  */
+    COVEST_FILL_UPPER = 1   /* entries with k2 >= k1 only; the lower triangle is untouched */
+} covest_fill;
+
+typedef struct {
+    covest_form form;
+    covest_precision prec;
+    covest_fill fill;
+    int normalize;          /* 1: R = C / K (default); 0: the paper's unnormalised C       */
+} covest_opts;
+
+/* Work counts of the method for one shape (Sec. 3.2-4.1):
+ *   K         number of window positions, (N-P+1)(M-Q+1)
+ *   n_uc      unique combinations, PQ + (P-1)(Q-1)                  (eq. 3.4)
+ *   um        distinct products, sum over combinations of
+ *             (N-|dr|)(M-|dc|)                                      (eqs. 3.5-3.6, 4.6)
+ *   eta       upper-triangle entries, PQ(PQ+1)/2                    (eqs. 3.8, 4.22)
+ *   segments  diagonal segments, sum over combinations of Q-|dc|    (Sec. 3.3)         */
+typedef struct {
+    int64_t K, n_uc, um, eta, segments;
+} covest_counts_t;
+
+/* One problem of a batch.  A and R are device pointers; the element type of R
+ * follows the batch's precision. */
+typedef struct {
+    const void *A;
+    void *R;
+    int32_t N, M, P, Q;
+} covest_problem;
+
+typedef struct covest_plan covest_plan;   /* opaque, owned by the library */
+
+/* Counts of the method for (N, M, P, Q).  Host only.  out must be non-null. */
+int covest_counts(int64_t N, int64_t M, int64_t P, int64_t Q, covest_counts_t *out);
+
+/* Device workspace (bytes) covest_forward needs for this shape and options.
+ * Host only; opts may be NULL (defaults: AUTO, FP64, FULL, normalize=1). */
+int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,
+                          const covest_opts *opts, size_t *bytes);
+
+/* R of the operation above (Sec. 2.2, eq. 2.2) for A (N x M, lda = M).
+ * ws must hold at least covest_workspace_size() bytes (NULL allowed when that
+ * size is 0).  The first call for a shape builds and caches its plan (host work
+ * plus a small device table); later calls only enqueue kernels. */
+int covest_forward(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,
+                   const covest_opts *opts, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* As covest_forward, for a strided view of A (row stride lda >= M elements)
+ * and of R (row stride ldr >= PQ elements). */
+int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t P, int64_t Q,
+                      void *R, int64_t ldr, const covest_opts *opts, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Adjoint of the forward map for a real loss L (PyTorch's convention for
+ * complex tensors: a gradient is dL/dRe + i dL/dIm).  dR (PQ x PQ complex64,
+ * full matrix) is the gradient of L with respect to every entry of R; with
+ * H = dR + dR^H, the result is dA = fold(H X) / K, where column (p, q) of X is
+ * V^{p,q} and fold adds row i + P*j of the product onto A[p+i][q+j].  dA
+ * (N x M complex64) is OVERWRITTEN.  normalize = 0 drops the 1/K.  Windows are
+ * recomputed from A; nothing is stored by the forward call. */
+int covest_backward_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,
+                                   const covest_opts *opts, size_t *bytes);
+int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t M, int64_t P,
+                    int64_t Q, const covest_opts *opts, void *ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* Batched forward (Sec. 3.4, 5.1: many matrices at once keep every core busy).
+ * covest_plan_batched_create copies the problem array, builds one work list for
+ * all problems (longest work first), allocates the plan's device tables and
+ * workspace, and captures the launches into a HIP graph on `stream`.  Every
+ * problem uses opts->prec (FP64 or FP32) with the recurrence form.
+ * covest_forward_batched replays that graph on `stream`: one launch for every
+ * instance.  The A and R buffers named at creation must stay valid. */
+int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,
+                               const covest_opts *opts, hipStream_t stream);
+int covest_forward_batched(covest_plan *plan, hipStream_t stream);
+int covest_plan_destroy(covest_plan *plan);
+
+/* Kernel timing for benchmarks: while enabled, every kernel the library
+ * launches is bracketed by HIP events on its stream and its duration is added
+ * to a per-kernel total.  covest_timing_read copies up to `cap` records (name,
+ * launches, total milliseconds) after synchronising the recorded events, and
+ * returns the number of records; covest_timing_reset clears them.  Host only. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} covest_timing_record;
+int covest_timing_enable(int on);
+int covest_timing_reset(void);
+int covest_timing_read(covest_timing_record *out, int cap);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *covest_last_error(void);
+
+/* COVEST_VERSION of the library. */
+int covest_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COVEST_H */

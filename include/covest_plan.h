@@ -1,0 +1,53 @@
+/*
+ * covest_plan.h -- host-only introspection of libcovest's recurrence plan,
+ * for tests and tools.  No device is needed.
+ *
+ * The recurrence (Sec. 3.3 of the paper: each product is computed once and
+ * every output entry has a single writer) splits the products of every unique
+ * combination (eq. 3.3) into a middle block shared by all window offsets,
+ * strips of individual rows and columns, and corner products.  These calls
+ * expose that split so a test can check that every product is owned by exactly
+ * one job and every upper-triangle entry by exactly one finalize item
+ * (Sec. 4.2-4.3).
+ *
+ * n_slots is the number of workgroups the plan assumes resident at once (two
+ * per compute unit: 512 on MI355X).  All arrays are caller-owned host memory.
+ */
+#ifndef COVEST_PLAN_H
+#define COVEST_PLAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t W0, W1;             /* ring widths: along columns (dc), along rows (dr)   */
+    int32_t Rm0, Rm1, Cm0, Cm1; /* middle rows [Rm0, Rm1) and columns [Cm0, Cm1)      */
+    int32_t n_ir, n_ic;         /* individual rows / columns                           */
+    int32_t lag_stride;         /* (2P-1)Q; lag (dr, dc) has index (dr+P-1)Q + dc       */
+    int32_t bandw;              /* columns per bulk unit                                */
+    int32_t n_bulk;             /* partial-sum rows                                     */
+    int32_t n_jobs, n_groups, n_items;
+    int64_t ws_bytes;           /* forward workspace                                    */
+    int64_t lds_main, lds_fin;  /* dynamic LDS bytes of the two kernels                 */
+    int64_t main_products;      /* distinct products kept by the main kernel            */
+    int64_t fin_products;       /* corner products computed by the finalize kernel      */
+} covest_plan_info;
+
+/* Job rows: 12 int32 each (mode, inst, group, out, u0, u1, x0, x1, c0, c1,
+ * tile_rows, tile_cols).  Group rows: 14 int32 each (orient, W, d1lo, d1hi,
+ * ch0, nch, v2lo, v2hi, lanes, slots, hr_lo, hr_hi, hc_lo, hc_hi).  Item rows:
+ * 5 int32 each (inst, dr, dc, bulk0, bulk1).  COVEST_ERR_SHAPE on a bad shape,
+ * COVEST_ERR_UNSUPPORTED when P or Q exceeds the recurrence's limit. */
+int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots,
+                         covest_plan_info *out);
+int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots,
+                       int32_t *jobs, int32_t *groups, int32_t *items);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COVEST_PLAN_H */

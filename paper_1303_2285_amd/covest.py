@@ -1,0 +1,327 @@
+"""Thin ctypes binding of libcovest (include/covest.h).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  If the
+built library is missing the import fails loudly; there is no fallback path.
+
+    R = covest_forward(A, P, Q)                 # complex128 R on A's device
+    dA = covest_backward(A, dR, P, Q)
+    plan = BatchedPlan([(A0, P0, Q0), ...]); plan.run(); plan.outputs
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcovest.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_SHAPE = -2
+ERR_WORKSPACE = -3
+ERR_HIP = -4
+ERR_UNSUPPORTED = -5
+ERR_PLAN_MISMATCH = -6
+
+FORMS = {"auto": 0, "recurrence": 1, "hankel": 2, "hankel_mfma": 2}
+PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3, "bf16": 4, "fp16": 5}
+FILLS = {"full": 0, "upper": 1}
+
+
+class CovestError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libcovest status {status}: {message}")
+        self.status = status
+
+
+class covest_opts(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("prec", ctypes.c_int), ("fill", ctypes.c_int),
+                ("normalize", ctypes.c_int)]
+
+
+class covest_counts_t(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("n_uc", ctypes.c_int64), ("um", ctypes.c_int64),
+                ("eta", ctypes.c_int64), ("segments", ctypes.c_int64)]
+
+
+class covest_problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("R", ctypes.c_void_p), ("N", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("P", ctypes.c_int32), ("Q", ctypes.c_int32)]
+
+
+class covest_timing_record(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class covest_plan_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("W0", "W1", "Rm0", "Rm1", "Cm0", "Cm1", "n_ir", "n_ic",
+                                               "lag_stride", "bandw", "n_bulk", "n_jobs", "n_groups",
+                                               "n_items")] + \
+               [(n, ctypes.c_int64) for n in ("ws_bytes", "lds_main", "lds_fin", "main_products",
+                                               "fin_products")]
+
+
+# Every symbol the headers declare, with its ctypes signature.
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+SIGNATURES = {
+    "covest_counts": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(covest_counts_t)]),
+    "covest_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "covest_forward": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, ctypes.POINTER(covest_opts), _vp,
+                              ctypes.c_size_t, _vp]),
+    "covest_forward_ex": (_int, [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64,
+                                 ctypes.POINTER(covest_opts), _vp, ctypes.c_size_t, _vp]),
+    "covest_backward_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "covest_backward": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
+                               _vp, ctypes.c_size_t, _vp]),
+    "covest_plan_batched_create": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_problem), _i64,
+                                          ctypes.POINTER(covest_opts), _vp]),
+    "covest_forward_batched": (_int, [_vp, _vp]),
+    "covest_plan_destroy": (_int, [_vp]),
+    "covest_timing_enable": (_int, [_int]),
+    "covest_timing_reset": (_int, []),
+    "covest_timing_read": (_int, [ctypes.POINTER(covest_timing_record), _int]),
+    "covest_last_error": (ctypes.c_char_p, []),
+    "covest_version": (_int, []),
+    # include/covest_plan.h
+    "covest_plan_info_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
+                                    ctypes.POINTER(covest_plan_info)]),
+    "covest_plan_tables": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libcovest.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libcovest.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        msg = lib().covest_last_error().decode(errors="replace")
+        raise CovestError(status, msg)
+
+
+def make_opts(form="auto", precision="fp64", fill="full", normalize=True) -> covest_opts:
+    o = covest_opts()
+    o.form = FORMS[form] if isinstance(form, str) else int(form)
+    o.prec = PRECS[precision] if isinstance(precision, str) else int(precision)
+    o.fill = FILLS[fill] if isinstance(fill, str) else int(fill)
+    o.normalize = 1 if normalize else 0
+    return o
+
+
+def counts(N: int, M: int, P: int, Q: int) -> dict:
+    """K, |UC|, UM, eta and the segment count of the method for one shape (host only)."""
+    c = covest_counts_t()
+    _check(lib().covest_counts(N, M, P, Q, ctypes.byref(c)))
+    return {"K": c.K, "n_uc": c.n_uc, "um": c.um, "eta": c.eta, "segments": c.segments}
+
+
+def workspace_size(N, M, P, Q, **kw) -> int:
+    o = make_opts(**kw)
+    n = ctypes.c_size_t(0)
+    _check(lib().covest_workspace_size(N, M, P, Q, ctypes.byref(o), ctypes.byref(n)))
+    return int(n.value)
+
+
+def backward_workspace_size(N, M, P, Q, **kw) -> int:
+    o = make_opts(**kw)
+    n = ctypes.c_size_t(0)
+    _check(lib().covest_backward_workspace_size(N, M, P, Q, ctypes.byref(o), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_input(A):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or not A.is_cuda:
+        raise TypeError("A must be a CUDA (HIP) tensor")
+    if A.dtype != torch.complex64:
+        raise TypeError("A must be complex64")
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D (N x M)")
+    if A.stride(1) != 1:
+        raise ValueError("A must have unit column stride")
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="full",
+                   normalize=True, out=None, workspace=None):
+    """R = (1/K) sum_{p,q} V^{p,q} (V^{p,q})^H for the complex64 N x M tensor A.
+
+    Returns a PQ x PQ tensor (complex128 for precision "fp64", complex64
+    otherwise) on A's device, computed on the current stream.
+    """
+    torch = _torch()
+    _check_input(A)
+    N, M = A.shape
+    o = make_opts(form, precision, fill, normalize)
+    PQ = P * Q
+    rdtype = torch.complex128 if o.prec == 0 else torch.complex64
+    if out is None:
+        R = torch.empty((PQ, PQ), dtype=rdtype, device=A.device)
+        if fill == "upper":
+            R.zero_()
+    else:
+        R = out
+        if R.dtype != rdtype or R.shape != (PQ, PQ) or R.stride(1) != 1:
+            raise ValueError("out has the wrong dtype, shape or layout")
+    need = workspace_size(N, M, P, Q, form=form, precision=precision, fill=fill,
+                          normalize=normalize)
+    if workspace is None or workspace.numel() < need:
+        ws, nbytes = _workspace(need, A.device)
+    else:
+        ws, nbytes = workspace, workspace.numel()
+    _check(lib().covest_forward_ex(
+        ctypes.c_void_p(A.data_ptr()), A.stride(0), N, M, P, Q, ctypes.c_void_p(R.data_ptr()),
+        R.stride(0), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+        nbytes, _stream_handle(A.device)))
+    return R
+
+
+def covest_backward(A, dR, P: int, Q: int, *, normalize=True, workspace=None):
+    """dA = fold((dR + dR^H) X) / K for the complex64 gradient dR (PQ x PQ)."""
+    torch = _torch()
+    _check_input(A)
+    N, M = A.shape
+    o = make_opts("auto", "fp32", "full", normalize)
+    dR = dR.to(torch.complex64).contiguous()
+    if dR.shape != (P * Q, P * Q):
+        raise ValueError("dR must be PQ x PQ")
+    dA = torch.empty_like(A)
+    need = backward_workspace_size(N, M, P, Q, precision="fp32", normalize=normalize)
+    ws, nbytes = _workspace(need, A.device) if workspace is None else (workspace, workspace.numel())
+    _check(lib().covest_backward(
+        ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(dR.data_ptr()), ctypes.c_void_p(dA.data_ptr()),
+        N, M, P, Q, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+        nbytes, _stream_handle(A.device)))
+    return dA
+
+
+@dataclass
+class _Problem:
+    A: object
+    P: int
+    Q: int
+
+
+class BatchedPlan:
+    """Many (A, P, Q) problems computed by one graph launch (covest_forward_batched)."""
+
+    def __init__(self, problems, precision="fp64", fill="full", normalize=True):
+        torch = _torch()
+        self._problems = [_Problem(A, int(P), int(Q)) for (A, P, Q) in problems]
+        o = make_opts("recurrence", precision, fill, normalize)
+        rdtype = torch.complex128 if o.prec == 0 else torch.complex64
+        arr = (covest_problem * len(self._problems))()
+        self.outputs = []
+        for i, pr in enumerate(self._problems):
+            _check_input(pr.A)
+            N, M = pr.A.shape
+            if pr.A.stride(0) != M:
+                raise ValueError("batched inputs must be contiguous")
+            R = torch.empty((pr.P * pr.Q, pr.P * pr.Q), dtype=rdtype, device=pr.A.device)
+            if fill == "upper":
+                R.zero_()
+            self.outputs.append(R)
+            arr[i] = covest_problem(pr.A.data_ptr(), R.data_ptr(), N, M, pr.P, pr.Q)
+        self._handle = ctypes.c_void_p(0)
+        dev = self._problems[0].A.device if self._problems else torch.device("cuda")
+        self._device = dev
+        _check(lib().covest_plan_batched_create(ctypes.byref(self._handle), arr, len(self._problems),
+                                                ctypes.byref(o), _stream_handle(dev)))
+
+    def run(self):
+        _check(lib().covest_forward_batched(self._handle, _stream_handle(self._device)))
+        return self.outputs
+
+    def close(self):
+        if self._handle and self._handle.value:
+            lib().covest_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def covest_forward_batched(plan: BatchedPlan):
+    return plan.run()
+
+
+# ---------------------------------------------------------------- timing ----
+
+def timing_enable(on: bool = True):
+    _check(lib().covest_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(lib().covest_timing_reset())
+
+
+def timing_read() -> dict:
+    recs = (covest_timing_record * 64)()
+    n = lib().covest_timing_read(recs, 64)
+    if n < 0:
+        _check(n)
+    return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].total_ms))
+            for i in range(min(n, 64))}
+
+
+def plan_info(N, M, P, Q, n_slots=512) -> dict:
+    """The recurrence plan's geometry for one shape (host only)."""
+    info = covest_plan_info()
+    _check(lib().covest_plan_info_get(N, M, P, Q, n_slots, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in covest_plan_info._fields_}
+
+
+def plan_tables(N, M, P, Q, n_slots=512):
+    """(jobs[n,12], groups[n,14], items[n,5]) int32 arrays of the recurrence plan."""
+    import numpy as np
+    info = plan_info(N, M, P, Q, n_slots)
+    jobs = np.zeros((info["n_jobs"], 12), dtype=np.int32)
+    groups = np.zeros((info["n_groups"], 14), dtype=np.int32)
+    items = np.zeros((info["n_items"], 5), dtype=np.int32)
+    _check(lib().covest_plan_tables(N, M, P, Q, n_slots, jobs.ctypes.data, groups.ctypes.data,
+                                    items.ctypes.data))
+    return info, jobs, groups, items
+
+
+def version() -> int:
+    return int(lib().covest_version())

@@ -1,0 +1,275 @@
+// plan.cpp -- host planning for the recurrence kernels.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+namespace covest {
+
+Counts method_counts(int64_t N, int64_t M, int64_t P, int64_t Q)
+{
+    Counts c{};
+    c.K = (N - P + 1) * (M - Q + 1);
+    c.n_uc = P * Q + (P - 1) * (Q - 1);
+    c.eta = P * Q * (P * Q + 1) / 2;
+    int64_t um = 0, seg = 0;
+    for (int64_t dc = 0; dc < Q; ++dc) {
+        for (int64_t dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
+            um += (N - std::llabs(dr)) * (M - dc);
+            seg += Q - dc;
+        }
+    }
+    c.um = um;
+    c.segments = seg;
+    return c;
+}
+
+static int ring_width(int n)
+{
+    if (n <= 4) return 4;
+    if (n <= 8) return 8;
+    if (n <= 12) return 12;
+    return 16;
+}
+
+// Lanes (d1, chunk) for d1 in [d1lo, d1hi) and d2 chunks covering [v2lo, v2hi)
+// from ch0, split so that a group has at most 64 lanes.
+static void add_groups(std::vector<LagGroup> &gs, int orient, int W, int d1lo, int d1hi, int ch0,
+                       int v2lo, int v2hi, std::vector<int> &ids)
+{
+    if (d1hi <= d1lo || v2hi <= v2lo) return;
+    const int nch = (v2hi - ch0 + W - 1) / W;
+    const int per = std::max(1, 64 / nch);
+    const int nd1 = d1hi - d1lo;
+    const int ngroups = (nd1 + per - 1) / per;
+    // balance the d1 ranges of the groups
+    for (int k = 0; k < ngroups; ++k) {
+        LagGroup g{};
+        g.orient = orient;
+        g.W = W;
+        g.d1lo = d1lo + (int)((int64_t)k * nd1 / ngroups);
+        g.d1hi = d1lo + (int)((int64_t)(k + 1) * nd1 / ngroups);
+        g.ch0 = ch0;
+        g.nch = nch;
+        g.v2lo = v2lo;
+        g.v2hi = v2hi;
+        g.lanes = (g.d1hi - g.d1lo) * nch;
+        g.slots = 64 / g.lanes;
+        g.hr_lo = std::min(0, g.d1lo);
+        g.hr_hi = std::max(0, g.d1hi - 1);
+        g.hc_lo = std::min(0, ch0);
+        g.hc_hi = std::max(0, ch0 + nch * W - 1);
+        ids.push_back((int)gs.size());
+        gs.push_back(g);
+    }
+}
+
+static size_t tile_bytes(int rows, int cols) { return (size_t)rows * (size_t)(cols | 1) * 16; }
+
+ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
+{
+    ShapePlan sp;
+    sp.N = N;
+    sp.M = M;
+    sp.P = P;
+    sp.Q = Q;
+    sp.W0 = ring_width(Q);
+    sp.W1 = ring_width(P);
+    sp.lag_stride = (2 * P - 1) * Q;
+    sp.bandw = kWaves * sp.W0;
+
+    // Middle rows: walked by column strips in blocks of W1.
+    sp.Rm0 = P - 1;
+    const int lenR = N - 2 * P + 2;
+    sp.Rm1 = sp.Rm0 + (lenR >= sp.W1 ? (lenR / sp.W1) * sp.W1 : 0);
+    // Middle columns: bulk bands of kWaves * W0.
+    sp.Cm0 = Q - 1;
+    const int lenC = M - 2 * Q + 2;
+    sp.Cm1 = sp.Cm0 + (lenC >= sp.bandw ? (lenC / sp.bandw) * sp.bandw : 0);
+    const int nMr = sp.Rm1 - sp.Rm0, nMc = sp.Cm1 - sp.Cm0;
+    sp.n_ir = N - nMr;
+    sp.n_ic = M - nMc;
+
+    // Lag groups.  Orientation 0 walks A's columns (ring over dc); orientation 1
+    // walks A's rows on the transposed tile (ring over dr).
+    std::vector<int> g0, g1;
+    add_groups(sp.groups, 0, sp.W0, 0, P, 0, 0, Q, g0);                  // type A
+    if (P > 1 && Q > 1) add_groups(sp.groups, 0, sp.W0, -(P - 1), 0, 1, 1, Q, g0);  // type B
+    add_groups(sp.groups, 1, sp.W1, 0, Q, 0, 0, P, g1);                  // type A
+    if (P > 1 && Q > 1) add_groups(sp.groups, 1, sp.W1, 1, Q, -(P - 1), -(P - 1), 0, g1);  // type B
+    sp.slots0 = sp.groups.empty() ? 1 : sp.groups[g0.front()].slots;
+
+    // --- job costs in wave-steps (one ring column of W complex MACs) -------
+    struct Strip { int group, x0, x1, c0, c1, out; double cost; };
+    std::vector<Strip> strips;
+    auto add_strips = [&](int gid, int lo, int hi, int out_base, int c0, int c1) {
+        const LagGroup &g = sp.groups[gid];
+        const int per = kWaves * g.slots;
+        for (int x = lo; x < hi; x += per) {
+            const int x1 = std::min(hi, x + per);
+            strips.push_back({gid, x, x1, c0, c1, out_base + (x - lo), (double)(c1 - c0) * g.W});
+        }
+    };
+    if (nMc > 0) {   // row strips: individual rows x middle columns
+        for (int gid : g0) {
+            add_strips(gid, 0, sp.Rm0, 0, sp.Cm0, sp.Cm1);
+            add_strips(gid, sp.Rm1, N, sp.Rm0, sp.Cm0, sp.Cm1);
+        }
+    }
+    if (nMr > 0) {   // column strips: individual columns x middle rows (B rows = A cols)
+        for (int gid : g1) {
+            add_strips(gid, 0, sp.Cm0, 0, sp.Rm0, sp.Rm1);
+            add_strips(gid, sp.Cm1, M, sp.Cm0, sp.Rm0, sp.Rm1);
+        }
+    }
+    double strip_total = 0.0, strip_max = 0.0;
+    for (const Strip &s : strips) {
+        strip_total += s.cost;
+        strip_max = std::max(strip_max, s.cost);
+    }
+
+    // Bulk units per orientation-0 group.
+    std::vector<int64_t> units(g0.size(), 0);
+    int64_t units_total = 0;
+    if (nMr > 0 && nMc > 0) {
+        for (size_t k = 0; k < g0.size(); ++k) {
+            const int S = sp.groups[g0[k]].slots;
+            units[k] = (int64_t)((nMr + S - 1) / S) * (nMc / sp.bandw);
+            units_total += units[k];
+        }
+    }
+    const double unit_cost = (double)sp.W0 * sp.W0;
+    const double bulk_total = (double)units_total * unit_cost;
+
+    int n_bulk = 0;
+    if (units_total > 0) {
+        const int n_strips = (int)strips.size();
+        const double ideal = (bulk_total + strip_total) / std::max(1, n_slots);
+        const double min_job = 32.0 * unit_cost;   // keep tiny problems to few jobs
+        double target;
+        if (strip_max <= ideal && n_strips < n_slots) {
+            n_bulk = n_slots - n_strips;
+            target = bulk_total / n_bulk;
+        } else {
+            target = std::max(strip_max, ideal);
+            n_bulk = (int)std::ceil(bulk_total / target);
+        }
+        if (target < min_job) n_bulk = (int)std::ceil(bulk_total / min_job);
+        n_bulk = (int)std::max<int64_t>(1, std::min<int64_t>(n_bulk, units_total));
+    }
+
+    // Split n_bulk over the groups in proportion to their units.
+    std::vector<int> njob(g0.size(), 0);
+    if (n_bulk > 0) {
+        int assigned = 0;
+        for (size_t k = 0; k < g0.size(); ++k) {
+            if (units[k] == 0) continue;
+            njob[k] = std::max<int>(1, (int)std::llround((double)n_bulk * units[k] / units_total));
+            njob[k] = (int)std::min<int64_t>(njob[k], units[k]);
+            assigned += njob[k];
+        }
+        (void)assigned;
+    }
+
+    // Bulk jobs, groups interleaved so that neighbouring jobs cover the same
+    // region of A.
+    std::vector<int> out_base(g0.size(), 0);
+    int outs = 0;
+    for (size_t k = 0; k < g0.size(); ++k) {
+        out_base[k] = outs;
+        outs += njob[k];
+    }
+    sp.n_bulk = outs;
+    int max_njob = 0;
+    for (int v : njob) max_njob = std::max(max_njob, v);
+    for (int j = 0; j < max_njob; ++j) {
+        for (size_t k = 0; k < g0.size(); ++k) {
+            if (j >= njob[k]) continue;
+            const LagGroup &g = sp.groups[g0[k]];
+            Job jb{};
+            jb.mode = kJobBulk;
+            jb.inst = 0;
+            jb.group = g0[k];
+            jb.out = out_base[k] + j;
+            jb.u0 = (int)((int64_t)j * units[k] / njob[k]);
+            jb.u1 = (int)((int64_t)(j + 1) * units[k] / njob[k]);
+            // rows per LDS sub-tile: a multiple of the slot count
+            const int S = g.slots;
+            const int cols = sp.bandw + g.hc_hi - g.hc_lo;
+            const int halo = g.hr_hi - g.hr_lo;
+            int tr = S;
+            while (tr + S <= std::max(S, 64) && tile_bytes(tr + S + halo, cols) <= kLdsBudget) tr += S;
+            jb.tile_rows = tr;
+            sp.jobs.push_back(jb);
+            sp.job_cost.push_back((double)(jb.u1 - jb.u0) * unit_cost);
+            sp.lds_main = std::max(sp.lds_main, tile_bytes(tr + halo, cols));
+            sp.lds_main = std::max(sp.lds_main, (size_t)kThreads * g.W * 16);
+        }
+    }
+    for (const Strip &s : strips) {
+        const LagGroup &g = sp.groups[s.group];
+        Job jb{};
+        jb.mode = kJobStrip;
+        jb.inst = 0;
+        jb.group = s.group;
+        jb.out = s.out;
+        jb.x0 = s.x0;
+        jb.x1 = s.x1;
+        jb.c0 = s.c0;
+        jb.c1 = s.c1;
+        const int rows = (s.x1 - s.x0) + g.hr_hi - g.hr_lo;
+        const int halo_c = g.hc_hi - g.hc_lo;
+        int tc = g.W;
+        while (tc + g.W <= (s.c1 - s.c0) && tile_bytes(rows, tc + g.W + halo_c) <= kLdsBudget) tc += g.W;
+        jb.tile_cols = tc;
+        sp.jobs.push_back(jb);
+        sp.job_cost.push_back(s.cost);
+        sp.lds_main = std::max(sp.lds_main, tile_bytes(rows, tc + halo_c));
+    }
+
+    // Finalize items: every unique combination (eq. 3.3).
+    for (int dc = 0; dc < Q; ++dc) {
+        for (int dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
+            FinItem it{};
+            it.inst = 0;
+            it.dr = dr;
+            it.dc = dc;
+            it.bulk0 = it.bulk1 = 0;
+            for (size_t k = 0; k < g0.size(); ++k) {
+                const LagGroup &g = sp.groups[g0[k]];
+                const bool in_type = (dr >= 0) == (g.d1lo >= 0);
+                if (in_type && dr >= g.d1lo && dr < g.d1hi && njob[k] > 0) {
+                    it.bulk0 = out_base[k];
+                    it.bulk1 = out_base[k] + njob[k];
+                }
+            }
+            sp.items.push_back(it);
+        }
+    }
+    sp.lds_fin = (size_t)(1 + sp.n_ir) * Q * 16;
+
+    sp.ws_bytes = (size_t)16 * sp.lag_stride *
+                  ((size_t)sp.n_bulk + (size_t)sp.n_ir + (size_t)sp.n_ic);
+
+    // Product counts (for throughput figures): the finalize computes the
+    // corner products (individual row and individual column) of every lag, the
+    // main kernel all the others.
+    const Counts cnt = method_counts(N, M, P, Q);
+    int64_t corner = 0;
+    for (int dc = 0; dc < Q; ++dc) {
+        for (int dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
+            const int rlo = std::max(0, -dr), rhi = N - std::max(0, dr);
+            const int chi = M - dc;
+            int64_t rows = 0, cols = 0;
+            for (int r = rlo; r < rhi; ++r) rows += (r < sp.Rm0 || r >= sp.Rm1) ? 1 : 0;
+            for (int c = 0; c < chi; ++c) cols += (c < sp.Cm0 || c >= sp.Cm1) ? 1 : 0;
+            corner += rows * cols;
+        }
+    }
+    sp.fin_products = corner;
+    sp.main_products = cnt.um - corner;
+    return sp;
+}
+
+}  // namespace covest

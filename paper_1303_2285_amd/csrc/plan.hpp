@@ -1,0 +1,48 @@
+// plan.hpp -- host-side planning of the recurrence: unique combinations,
+// lag groups, the middle / individual split, the job list of the main kernel
+// and the finalize items.  No HIP calls; usable without a GPU.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "covest_internal.hpp"
+
+namespace covest {
+
+struct Counts {
+    int64_t K, n_uc, um, eta, segments;
+};
+
+// Sec. 3.2-4.1 counts: K positions, |UC| (eq. 3.4), UM = sum of
+// (N-|dr|)(M-|dc|) over UC (eqs. 3.5-3.6), eta = PQ(PQ+1)/2 (eq. 4.22) and the
+// number of diagonal segments, sum of Q-|dc| over UC.
+Counts method_counts(int64_t N, int64_t M, int64_t P, int64_t Q);
+
+// Plan of one problem shape.  Job::inst is 0, outputs are relative to this
+// shape's own workspace; batched plans offset them.
+struct ShapePlan {
+    int N = 0, M = 0, P = 0, Q = 0;
+    int W0 = 0, W1 = 0;
+    int Rm0 = 0, Rm1 = 0, Cm0 = 0, Cm1 = 0, n_ir = 0, n_ic = 0;
+    int lag_stride = 0, bandw = 0, slots0 = 0;
+    int n_bulk = 0;                      // partial rows
+    std::vector<LagGroup> groups;
+    std::vector<Job> jobs;
+    std::vector<FinItem> items;
+    std::vector<double> job_cost;        // estimated wave-steps per job
+    size_t lds_main = 0, lds_fin = 0;
+    size_t ws_bytes = 0;                 // partial + zr + zc, FP64 complex
+    int64_t main_products = 0;           // distinct products the main kernel keeps
+    int64_t fin_products = 0;            // corner products the finalize computes
+};
+
+// n_slots: workgroups resident at once on the target device (2 per CU).
+ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots);
+
+// Limits of the recurrence form.
+constexpr int kMaxWindow = 64;           // P, Q <= kMaxWindow
+constexpr size_t kLdsBudget = 72 * 1024; // per workgroup, so two fit in 160 KB
+
+}  // namespace covest

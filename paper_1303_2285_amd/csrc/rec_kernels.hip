@@ -1,0 +1,404 @@
+// rec_kernels.hip -- the diagonal-segment recurrence (kernel family a) for
+// gfx950.
+//
+// The paper's combination-parallel method (Sec. 3.3, Algorithm 1) computes each
+// product A[r][c] * conj(A[r+dr][c+dc]) once and adds it to every output entry
+// of its combination; those entries lie on one diagonal of R, in Q-|dc|
+// segments of P-|dr| entries (Sec. 3.3, eq. 3.8).  Here the additions are not
+// repeated either: entry (i1, j1) of combination (dr, dc) is the sum of the
+// product grid over a Kr x Kc box, every box contains a common middle region,
+// and neighbouring entries of a segment differ by one row (or column) of
+// products entering the box and one leaving it (the shift rule of Sec. 3.3).
+//
+// rec_main      one launch for all products: bulk jobs (middle x middle, one sum
+//               per lag), row-strip jobs (middle columns, one sum per
+//               individual row) and column-strip jobs (middle rows, one sum per
+//               individual column; walked on the transposed tile).
+// rec_finalize  one wave per unique combination: adds the corner products,
+//               slides the box along the segment (FP64 carries), divides by K
+//               and writes the segment entries (upper triangle and mirror).
+//
+// Arithmetic: complex64 inputs are widened to FP64 once, when a tile is staged
+// in LDS.  A product of two floats is exact in FP64, so every sum is an FP64
+// sum of exact products; on small-integer inputs every intermediate is an
+// integer below 2^53 and the result is bit-exact.
+#include <hip/hip_runtime.h>
+
+#include "covest_internal.hpp"
+
+namespace covest {
+
+// acc += x * conj(y)
+__device__ __forceinline__ void cmac(double2 &acc, const double2 x, const double2 y)
+{
+    acc.x = fma(x.x, y.x, acc.x);
+    acc.x = fma(x.y, y.y, acc.x);
+    acc.y = fma(x.y, y.x, acc.y);
+    acc.y = fma(-x.x, y.y, acc.y);
+}
+
+__device__ __forceinline__ double2 cprod(const double2 x, const double2 y)
+{
+    double2 r = make_double2(0.0, 0.0);
+    cmac(r, x, y);
+    return r;
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+__device__ __forceinline__ double2 ld_a(const Inst &in, int r, int c)
+{
+    const float2 v = static_cast<const float2 *>(in.A)[(int64_t)r * in.lda + c];
+    return make_double2((double)v.x, (double)v.y);
+}
+
+// Ring walk along one tile row.  xs[c] is the first factor at walk column c,
+// ys[c + w] the second factor of lag w.  Per column: one LDS read of the new
+// second factor, one (broadcast) read of the first factor, W complex MACs.
+template <int W>
+__device__ __forceinline__ void ring_walk(const double2 *__restrict__ xs,
+                                          const double2 *__restrict__ ys, int nblocks,
+                                          double2 (&acc)[W])
+{
+    double2 ring[W];
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) ring[k] = ys[k];
+    for (int b = 0; b < nblocks; ++b) {
+        const double2 *xb = xs + b * W;
+        const double2 *yb = ys + b * W;
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            ring[(u + W - 1) % W] = yb[u + W - 1];
+            const double2 x = xb[u];
+#pragma unroll
+            for (int w = 0; w < W; ++w) cmac(acc[w], x, ring[(u + w) % W]);
+        }
+    }
+}
+
+// Stage B[tr0 + i][tc0 + j] (i < nr, j < nc) as FP64 into lds[i * stride + j];
+// B = A (orient 0) or A^T (orient 1); entries outside A are zero.
+__device__ __forceinline__ void fill_tile(double2 *lds, int stride, const Inst &in, int orient,
+                                          int tr0, int nr, int tc0, int nc)
+{
+    const float2 *A = static_cast<const float2 *>(in.A);
+    const int total = nr * nc;
+    if (orient == 0) {
+        for (int e = threadIdx.x; e < total; e += kThreads) {
+            const int i = e / nc, j = e - i * nc;
+            const int r = tr0 + i, c = tc0 + j;
+            double2 v = make_double2(0.0, 0.0);
+            if (r >= 0 && r < in.N && c >= 0 && c < in.M) {
+                const float2 a = A[(int64_t)r * in.lda + c];
+                v = make_double2((double)a.x, (double)a.y);
+            }
+            lds[i * stride + j] = v;
+        }
+    } else {
+        // i runs fastest so that consecutive threads read consecutive A columns
+        for (int e = threadIdx.x; e < total; e += kThreads) {
+            const int j = e / nr, i = e - j * nr;
+            const int ac = tr0 + i, ar = tc0 + j;
+            double2 v = make_double2(0.0, 0.0);
+            if (ar >= 0 && ar < in.N && ac >= 0 && ac < in.M) {
+                const float2 a = A[(int64_t)ar * in.lda + ac];
+                v = make_double2((double)a.x, (double)a.y);
+            }
+            lds[i * stride + j] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ int lag_index(const Inst &in, int orient, int d1, int d2)
+{
+    const int dr = orient ? d2 : d1;
+    const int dc = orient ? d1 : d2;
+    return (dr + in.P - 1) * in.Q + dc;
+}
+
+template <int W>
+__device__ void run_bulk(const Job &job, const Inst &in, const LagGroup &g, double2 *lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int L = g.lanes, S = g.slots;
+    const int slot = lane / L, li = lane - slot * L;
+    const bool active = slot < S;
+    const int d1 = g.d1lo + li / g.nch;
+    const int d2 = g.ch0 + (li % g.nch) * W;
+
+    double2 acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = make_double2(0.0, 0.0);
+
+    const int nrg = (in.Rm1 - in.Rm0 + S - 1) / S;
+    const int bandw = kWaves * W;
+    int u = job.u0;
+    while (u < job.u1) {
+        const int band = u / nrg, rg = u - band * nrg;
+        const int rg_end = min(nrg, rg + (job.u1 - u));
+        const int xr_a = in.Rm0 + rg * S;
+        const int xr_b = min(in.Rm1, in.Rm0 + rg_end * S);
+        const int xc = in.Cm0 + band * bandw;
+        for (int r = xr_a; r < xr_b; r += job.tile_rows) {
+            const int r_end = min(xr_b, r + job.tile_rows);
+            const int tr0 = r + g.hr_lo, nr = r_end + g.hr_hi - tr0;
+            const int tc0 = xc + g.hc_lo, nc = xc + bandw + g.hc_hi - tc0;
+            const int stride = nc | 1;
+            __syncthreads();
+            fill_tile(lds, stride, in, 0, tr0, nr, tc0, nc);
+            __syncthreads();
+            if (active) {
+                const int xcw = xc + wave * W;
+                for (int t = r + slot; t < r_end; t += S) {
+                    const double2 *xs = lds + (t - tr0) * stride + (xcw - tc0);
+                    const double2 *ys = lds + (t + d1 - tr0) * stride + (xcw + d2 - tc0);
+                    ring_walk<W>(xs, ys, 1, acc);
+                }
+            }
+        }
+        u += rg_end - rg;
+    }
+
+    // Sum the lanes that hold the same lags (every wave and slot), fixed order.
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < W; ++w) lds[(wave * 64 + lane) * W + w] = acc[w];
+    __syncthreads();
+    double *out = in.partial + (int64_t)job.out * in.lag_stride * 2;
+    for (int e = threadIdx.x; e < L * W; e += kThreads) {
+        const int l2 = e / W, w = e - l2 * W;
+        const int e1 = g.d1lo + l2 / g.nch;
+        const int e2 = g.ch0 + (l2 % g.nch) * W + w;
+        if (e2 < g.v2lo || e2 >= g.v2hi) continue;
+        double2 s = make_double2(0.0, 0.0);
+        for (int wv = 0; wv < kWaves; ++wv)
+            for (int sl = 0; sl < S; ++sl) s = cadd(s, lds[(wv * 64 + sl * L + l2) * W + w]);
+        const int idx = lag_index(in, 0, e1, e2);
+        reinterpret_cast<double2 *>(out)[idx] = s;
+    }
+}
+
+template <int W>
+__device__ void run_strip(const Job &job, const Inst &in, const LagGroup &g, double2 *lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int L = g.lanes, S = g.slots;
+    const int slot = lane / L, li = lane - slot * L;
+    const int d1 = g.d1lo + li / g.nch;
+    const int d2 = g.ch0 + (li % g.nch) * W;
+    const int t = job.x0 + wave * S + slot;
+    const bool mine = slot < S && t < job.x1;
+
+    double2 acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = make_double2(0.0, 0.0);
+
+    const int tr0 = job.x0 + g.hr_lo, nr = job.x1 + g.hr_hi - tr0;
+    for (int c = job.c0; c < job.c1; c += job.tile_cols) {
+        const int c_end = min(job.c1, c + job.tile_cols);
+        const int tc0 = c + g.hc_lo, nc = c_end + g.hc_hi - tc0;
+        const int stride = nc | 1;
+        __syncthreads();
+        fill_tile(lds, stride, in, g.orient, tr0, nr, tc0, nc);
+        __syncthreads();
+        if (mine) {
+            const double2 *xs = lds + (t - tr0) * stride + (c - tc0);
+            const double2 *ys = lds + (t + d1 - tr0) * stride + (c + d2 - tc0);
+            ring_walk<W>(xs, ys, (c_end - c) / W, acc);
+        }
+    }
+    if (!mine) return;
+    double *base = g.orient ? in.zc : in.zr;
+    double2 *row = reinterpret_cast<double2 *>(base + (int64_t)(job.out + (t - job.x0)) * in.lag_stride * 2);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const int e2 = d2 + w;
+        if (e2 >= g.v2lo && e2 < g.v2hi) row[lag_index(in, g.orient, d1, e2)] = acc[w];
+    }
+}
+
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    // Workgroup b runs on XCD b % 8.  Give the workgroups of one XCD a
+    // contiguous range of jobs (jobs are generated in spatial order), so an
+    // XCD's L2 holds one region of A.
+    const int per = n / 8;
+    return (b % 8) * per + b / 8;
+}
+
+__global__ void __launch_bounds__(kThreads, 2) rec_main(MainArgs ma)
+{
+    extern __shared__ double2 lds[];
+    int b = blockIdx.x;
+    if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
+    const Job job = ma.jobs[b];
+    const Inst in = ma.use_inline ? ma.inst_inline : ma.insts[job.inst];
+    const LagGroup g = ma.groups[job.group];
+    if (job.mode == kJobBulk) {
+        switch (g.W) {
+        case 16: run_bulk<16>(job, in, g, lds); break;
+        case 12: run_bulk<12>(job, in, g, lds); break;
+        case 8: run_bulk<8>(job, in, g, lds); break;
+        default: run_bulk<4>(job, in, g, lds); break;
+        }
+    } else {
+        switch (g.W) {
+        case 16: run_strip<16>(job, in, g, lds); break;
+        case 12: run_strip<12>(job, in, g, lds); break;
+        case 8: run_strip<8>(job, in, g, lds); break;
+        default: run_strip<4>(job, in, g, lds); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one wave per unique combination.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double2 wave_sum(double2 v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        v.x += __shfl_xor(v.x, off, 64);
+        v.y += __shfl_xor(v.y, off, 64);
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_r(const Inst &in, int k1, int k2, double2 s, bool diag)
+{
+    double2 v = s;
+    if (in.normalize) {
+        const double K = (double)in.Kr * (double)in.Kc;
+        v.x = s.x / K;
+        v.y = s.y / K;
+    }
+    if (diag) v.y = 0.0;
+    if (in.out_fp64) {
+        double2 *R = static_cast<double2 *>(in.R);
+        R[(int64_t)k1 * in.ldr + k2] = v;
+        if (in.fill_full && !diag) R[(int64_t)k2 * in.ldr + k1] = make_double2(v.x, -v.y);
+    } else {
+        float2 *R = static_cast<float2 *>(in.R);
+        const float2 f = make_float2((float)v.x, (float)v.y);
+        R[(int64_t)k1 * in.ldr + k2] = f;
+        if (in.fill_full && !diag) R[(int64_t)k2 * in.ldr + k1] = make_float2(f.x, -f.y);
+    }
+}
+
+__global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
+{
+    extern __shared__ double2 cs[];
+    const FinItem it = fa.items[blockIdx.x];
+    const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
+    const int P = in.P, N = in.N, Kr = in.Kr, Kc = in.Kc;
+    const int dr = it.dr, dc = it.dc;
+    const int lag = (dr + P - 1) * in.Q + dc;
+    const int64_t ls2 = (int64_t)in.lag_stride;
+    const int lane = threadIdx.x;
+    const int rlo = max(0, -dr), rhi = N - max(0, dr);
+    const int nr = P - abs(dr);
+    const int nc = in.Q - dc;
+    const int Rm0 = in.Rm0, Rm1 = in.Rm1, Cm0 = in.Cm0, Cm1 = in.Cm1;
+    const double2 *partial = reinterpret_cast<const double2 *>(in.partial);
+    const double2 *zr = reinterpret_cast<const double2 *>(in.zr);
+    const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
+    const bool has_mr = Rm1 > Rm0;   // column strips exist (they walk the middle rows)
+    const bool has_mc = Cm1 > Cm0;   // row strips exist (they walk the middle columns)
+
+    // Middle sum of this lag: fixed-order sum of the bulk partials.
+    double2 zm = make_double2(0.0, 0.0);
+    for (int j = it.bulk0 + lane; j < it.bulk1; j += 64) zm = cadd(zm, partial[j * ls2 + lag]);
+    zm = wave_sum(zm);
+
+    // Step 1: for every row class (the middle rows as one class, then each
+    // individual row that some box of this lag contains), the sums over the
+    // column range of every column offset b, by sliding along b.
+    const int ncls = 1 + in.n_ir;
+    for (int e = lane; e < ncls; e += 64) {
+        double2 *out = cs + e * nc;
+        if (e == 0) {
+            if (!has_mr) {
+                for (int b = 0; b < nc; ++b) out[b] = make_double2(0.0, 0.0);
+                continue;
+            }
+            double2 s = zm;
+            for (int c = 0; c < min(Cm0, Kc); ++c) s = cadd(s, zc[c * ls2 + lag]);
+            for (int c = Cm1; c < Kc; ++c) s = cadd(s, zc[(Cm0 + c - Cm1) * ls2 + lag]);
+            out[0] = s;
+            for (int b = 0; b + 1 < nc; ++b) {
+                const int cin = b + Kc;   // enters: an individual column >= Cm1
+                s = csub(s, zc[b * ls2 + lag]);
+                s = cadd(s, zc[(Cm0 + cin - Cm1) * ls2 + lag]);
+                out[b + 1] = s;
+            }
+        } else {
+            const int rho = e - 1;
+            const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+            if (r < rlo || r >= rhi) continue;
+            double2 s = has_mc ? zr[rho * ls2 + lag] : make_double2(0.0, 0.0);
+            for (int c = 0; c < min(Cm0, Kc); ++c) s = cadd(s, cprod(ld_a(in, r, c), ld_a(in, r + dr, c + dc)));
+            for (int c = Cm1; c < Kc; ++c) s = cadd(s, cprod(ld_a(in, r, c), ld_a(in, r + dr, c + dc)));
+            out[0] = s;
+            for (int b = 0; b + 1 < nc; ++b) {
+                const int cin = b + Kc;
+                s = csub(s, cprod(ld_a(in, r, b), ld_a(in, r + dr, b + dc)));
+                s = cadd(s, cprod(ld_a(in, r, cin), ld_a(in, r + dr, cin + dc)));
+                out[b + 1] = s;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Step 2: for each column offset b, slide the box down the segment.
+    for (int b = lane; b < nc; b += 64) {
+        double2 s = cs[b];
+        for (int r = rlo; r < min(Rm0, rlo + Kr); ++r) s = cadd(s, cs[(1 + r) * nc + b]);
+        for (int r = max(Rm1, rlo); r < rlo + Kr; ++r) s = cadd(s, cs[(1 + Rm0 + r - Rm1) * nc + b]);
+        for (int a = 0; a < nr; ++a) {
+            const int i1 = rlo + a;
+            const int k1 = i1 + P * b;
+            const int k2 = (i1 + dr) + P * (b + dc);
+            store_r(in, k1, k2, s, dr == 0 && dc == 0);
+            if (a + 1 < nr) {
+                const int rout = i1;          // an individual row < Rm0
+                const int rin = i1 + Kr;      // an individual row >= Rm1
+                s = csub(s, cs[(1 + rout) * nc + b]);
+                s = cadd(s, cs[(1 + Rm0 + rin - Rm1) * nc + b]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launch helpers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_rec_main(const MainArgs &ma, int n_blocks, size_t lds_bytes, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_main),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(rec_main, dim3(n_blocks), dim3(kThreads), lds_bytes, stream, ma);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_finalize),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
+    return hipGetLastError();
+}
+
+}  // namespace covest
