@@ -105,6 +105,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libcovest.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime under the same soname.  Load it
+        # first so that libcovest binds to that one copy; a second runtime in
+        # the process would not see the device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
@@ -136,11 +140,17 @@ def counts(N: int, M: int, P: int, Q: int) -> dict:
     return {"K": c.K, "n_uc": c.n_uc, "um": c.um, "eta": c.eta, "segments": c.segments}
 
 
+_ws_cache: dict = {}
+
+
 def workspace_size(N, M, P, Q, **kw) -> int:
-    o = make_opts(**kw)
-    n = ctypes.c_size_t(0)
-    _check(lib().covest_workspace_size(N, M, P, Q, ctypes.byref(o), ctypes.byref(n)))
-    return int(n.value)
+    key = (N, M, P, Q, tuple(sorted(kw.items())))
+    if key not in _ws_cache:
+        o = make_opts(**kw)
+        n = ctypes.c_size_t(0)
+        _check(lib().covest_workspace_size(N, M, P, Q, ctypes.byref(o), ctypes.byref(n)))
+        _ws_cache[key] = int(n.value)
+    return _ws_cache[key]
 
 
 def backward_workspace_size(N, M, P, Q, **kw) -> int:

@@ -182,13 +182,21 @@ int get_plan(int N, int M, int P, int Q, DevPlan **out)
     return COVEST_OK;
 }
 
-int shape_plan_only(int N, int M, int P, int Q, ShapePlan *sp)
+std::mutex g_hmu;
+std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<const ShapePlan>> g_host_plans;
+
+// Host-only planning, cached (workspace queries must work without a device).
+std::shared_ptr<const ShapePlan> host_plan(int N, int M, int P, int Q)
 {
-    // Host-only planning (workspace queries must work without a device).
     int dev = 0, slots = 512;
     if (hipGetDevice(&dev) == hipSuccess) slots = n_slots_for_device(dev);
-    *sp = make_shape_plan(N, M, P, Q, slots);
-    return COVEST_OK;
+    auto key = std::make_tuple(slots, N, M, P, Q);
+    std::lock_guard<std::mutex> lk(g_hmu);
+    auto it = g_host_plans.find(key);
+    if (it != g_host_plans.end()) return it->second;
+    auto sp = std::make_shared<const ShapePlan>(make_shape_plan(N, M, P, Q, slots));
+    g_host_plans.emplace(key, sp);
+    return sp;
 }
 
 Inst make_inst(const ShapePlan &sp, const void *A, int64_t lda, void *R, int64_t ldr, void *ws,
@@ -268,7 +276,7 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     fa.use_inline = 1;
     fa.inst_inline = in;
     HIP_TRY(timed("rec_finalize", stream, [&] {
-        return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, stream);
+        return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, sp.fin_table, stream);
     }));
     return finish_call(stream);
 }
@@ -308,9 +316,7 @@ int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q, const cove
     if (use_recurrence(o)) {
         if (P > kMaxWindow || Q > kMaxWindow)
             return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
-        ShapePlan sp;
-        shape_plan_only((int)N, (int)M, (int)P, (int)Q, &sp);
-        *bytes = sp.ws_bytes;
+        *bytes = host_plan((int)N, (int)M, (int)P, (int)Q)->ws_bytes;
         return ok();
     }
     return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form is not available in this build");

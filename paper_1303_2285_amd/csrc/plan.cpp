@@ -247,7 +247,9 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
             sp.items.push_back(it);
         }
     }
-    sp.lds_fin = (size_t)(1 + sp.n_ir) * Q * 16;
+    const size_t table = (size_t)(1 + sp.n_ir) * sp.n_ic * 16;
+    sp.fin_table = table <= kFinTableMax;
+    sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
 
     sp.ws_bytes = (size_t)16 * sp.lag_stride *
                   ((size_t)sp.n_bulk + (size_t)sp.n_ir + (size_t)sp.n_ic);

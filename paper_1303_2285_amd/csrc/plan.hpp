@@ -33,6 +33,7 @@ struct ShapePlan {
     std::vector<FinItem> items;
     std::vector<double> job_cost;        // estimated wave-steps per job
     size_t lds_main = 0, lds_fin = 0;
+    bool fin_table = false;              // finalize through the LDS table variant
     size_t ws_bytes = 0;                 // partial + zr + zc, FP64 complex
     int64_t main_products = 0;           // distinct products the main kernel keeps
     int64_t fin_products = 0;            // corner products the finalize computes
@@ -44,5 +45,6 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots);
 // Limits of the recurrence form.
 constexpr int kMaxWindow = 64;           // P, Q <= kMaxWindow
 constexpr size_t kLdsBudget = 72 * 1024; // per workgroup, so two fit in 160 KB
+constexpr size_t kFinTableMax = 96 * 1024;  // largest LDS table of the table finalize
 
 }  // namespace covest

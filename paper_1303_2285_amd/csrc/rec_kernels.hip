@@ -371,6 +371,110 @@ __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
     }
 }
 
+// Table variant of the finalize (256 threads, one unique combination): every
+// product the sliding needs is computed at once into an LDS table (rows:
+// the middle class and each individual row; columns: the individual columns),
+// so the loads overlap instead of forming one long dependent chain per lane.
+// The sums run in the same order as rec_finalize.
+__global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
+{
+    extern __shared__ double2 V[];
+    __shared__ double2 red[256];
+    const FinItem it = fa.items[blockIdx.x];
+    const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
+    const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
+    const int dr = it.dr, dc = it.dc;
+    const int lag = (dr + P - 1) * in.Q + dc;
+    const int64_t ls2 = (int64_t)in.lag_stride;
+    const int tid = threadIdx.x;
+    const int rlo = max(0, -dr), rhi = N - max(0, dr);
+    const int nr = P - abs(dr);
+    const int nc = in.Q - dc;
+    const int Rm0 = in.Rm0, Rm1 = in.Rm1, Cm0 = in.Cm0, Cm1 = in.Cm1;
+    const bool has_mr = Rm1 > Rm0, has_mc = Cm1 > Cm0;
+    const double2 *partial = reinterpret_cast<const double2 *>(in.partial);
+    const double2 *zr = reinterpret_cast<const double2 *>(in.zr);
+    const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
+    const float2 *A = static_cast<const float2 *>(in.A);
+    const int nV = in.n_ic;
+    const int ncls = 1 + in.n_ir;
+
+    // Middle sum: fixed-order tree over the bulk partials.
+    double2 z = make_double2(0.0, 0.0);
+    for (int j = it.bulk0 + tid; j < it.bulk1; j += 256) z = cadd(z, partial[j * ls2 + lag]);
+    red[tid] = z;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = cadd(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const double2 zm = red[0];
+
+    // Phase A: the table of individual-column terms of every row class.
+    for (int e = tid; e < ncls * nV; e += 256) {
+        const int cls = e / nV, gi = e - cls * nV;
+        const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
+        double2 v = make_double2(0.0, 0.0);
+        if (c + dc < M) {
+            if (cls == 0) {
+                if (has_mr) v = zc[gi * ls2 + lag];
+            } else {
+                const int rho = cls - 1;
+                const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+                if (r >= rlo && r < rhi) {
+                    const float2 x = A[(int64_t)r * in.lda + c];
+                    const float2 y = A[(int64_t)(r + dr) * in.lda + c + dc];
+                    v = cprod(make_double2(x.x, x.y), make_double2(y.x, y.y));
+                }
+            }
+        }
+        V[e] = v;
+    }
+    __syncthreads();
+
+    // Phase B: per class, the sums over the column range of every offset b,
+    // written in place over the (already consumed) left-column terms.
+    for (int cls = tid; cls < ncls; cls += 256) {
+        double2 s;
+        if (cls == 0) {
+            s = has_mr ? zm : make_double2(0.0, 0.0);
+        } else {
+            const int rho = cls - 1;
+            const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+            if (r < rlo || r >= rhi) continue;
+            s = has_mc ? zr[rho * ls2 + lag] : make_double2(0.0, 0.0);
+        }
+        double2 *row = V + cls * nV;
+        for (int gi = 0; gi < min(Cm0, Kc); ++gi) s = cadd(s, row[gi]);
+        for (int c = Cm1; c < Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);
+        for (int b = 0; b + 1 < nc; ++b) {
+            const double2 vo = row[b];
+            const double2 vi = row[Cm0 + (b + Kc) - Cm1];
+            row[b] = s;
+            s = cadd(csub(s, vo), vi);
+        }
+        row[nc - 1] = s;
+    }
+    __syncthreads();
+
+    // Phase C: for each column offset b, slide the box down the segment.
+    for (int b = tid; b < nc; b += 256) {
+        double2 s = V[b];
+        for (int r = rlo; r < min(Rm0, rlo + Kr); ++r) s = cadd(s, V[(1 + r) * nV + b]);
+        for (int r = max(Rm1, rlo); r < rlo + Kr; ++r) s = cadd(s, V[(1 + Rm0 + r - Rm1) * nV + b]);
+        for (int a = 0; a < nr; ++a) {
+            const int i1 = rlo + a;
+            const int k1 = i1 + P * b;
+            const int k2 = (i1 + dr) + P * (b + dc);
+            store_r(in, k1, k2, s, dr == 0 && dc == 0);
+            if (a + 1 < nr) {
+                s = csub(s, V[(1 + i1) * nV + b]);
+                s = cadd(s, V[(1 + Rm0 + i1 + Kr - Rm1) * nV + b]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host launch helpers
 // ---------------------------------------------------------------------------
@@ -388,16 +492,23 @@ hipError_t launch_rec_main(const MainArgs &ma, int n_blocks, size_t lds_bytes, h
     return hipGetLastError();
 }
 
-hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, hipStream_t stream)
+hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
+                               hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_finalize),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_finalize_tab),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
+    if (table)
+        hipLaunchKernelGGL(rec_finalize_tab, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else
+        hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
     return hipGetLastError();
 }
 

@@ -127,6 +127,7 @@ EDGE_SHAPES = [
     (1, 1, 1, 1), (5, 7, 5, 7), (5, 7, 1, 1), (9, 4, 3, 4), (33, 17, 1, 16), (17, 33, 16, 1),
     (40, 33, 4, 16), (97, 131, 12, 4), (131, 97, 5, 13), (64, 64, 32, 32), (70, 66, 33, 2),
     (200, 150, 20, 24), (128, 256, 16, 8), (300, 64, 16, 12), (48, 48, 8, 8),
+    (130, 130, 40, 40),   # finalize table too large for LDS: the per-lane variant
 ]
 
 
