@@ -176,7 +176,7 @@ int get_plan(int N, int M, int P, int Q, DevPlan **out)
     HIP_TRY(upload(&dp->d_jobs, dp->sp.jobs));
     HIP_TRY(upload(&dp->d_groups, dp->sp.groups));
     HIP_TRY(upload(&dp->d_items, dp->sp.items));
-    dp->xcd_remap = (!dp->sp.jobs.empty() && dp->sp.jobs.size() % 8 == 0) ? 1 : 0;
+    dp->xcd_remap = dp->sp.jobs.empty() ? 0 : 1;
     *out = dp.get();
     g_plans.emplace(key, std::move(dp));
     return COVEST_OK;
@@ -281,6 +281,112 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     return finish_call(stream);
 }
 
+// ------------------------------------------------------------ plain form ----
+int hankel_prec(covest_precision p)
+{
+    switch (p) {
+    case COVEST_PREC_FP32: return kPrecF32;
+    case COVEST_PREC_BF16X3: return kPrecBF16x3;
+    case COVEST_PREC_FP16X3: return kPrecF16x3;
+    case COVEST_PREC_BF16: return kPrecBF16;
+    case COVEST_PREC_FP16: return kPrecF16;
+    default: return -1;
+    }
+}
+
+struct DevHankel {
+    HankelPlan hp;
+    HItem *d_items = nullptr;
+    HTile *d_tiles = nullptr;
+};
+std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<DevHankel>> g_hplans;
+
+int cu_count(int dev)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+std::shared_ptr<const HankelPlan> host_hankel_plan(int N, int M, int P, int Q, int prec)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, std::shared_ptr<const HankelPlan>> cache;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) cus = cu_count(dev);
+    auto key = std::make_tuple(cus, N, M, P, Q, prec);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    auto hp = std::make_shared<const HankelPlan>(make_hankel_plan(N, M, P, Q, prec, cus));
+    cache.emplace(key, hp);
+    return hp;
+}
+
+int get_hankel_plan(int N, int M, int P, int Q, int prec, DevHankel **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto key = std::make_tuple(dev, N, M, P, Q, prec);
+    std::lock_guard<std::mutex> lk(g_pmu);
+    auto it = g_hplans.find(key);
+    if (it != g_hplans.end()) {
+        *out = it->second.get();
+        return COVEST_OK;
+    }
+    auto dh = std::make_unique<DevHankel>();
+    dh->hp = make_hankel_plan(N, M, P, Q, prec, cu_count(dev));
+    HIP_TRY(upload(&dh->d_items, dh->hp.items));
+    HIP_TRY(upload(&dh->d_tiles, dh->hp.tiles));
+    *out = dh.get();
+    g_hplans.emplace(key, std::move(dh));
+    return COVEST_OK;
+}
+
+int hankel_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
+                   const covest_opts &o, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const int prec = hankel_prec(o.prec);
+    if (prec < 0) return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form has no FP64 precision");
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form supports P, Q <= %d", kMaxWindow);
+    DevHankel *dh = nullptr;
+    int st = get_hankel_plan(N, M, P, Q, prec, &dh);
+    if (st != COVEST_OK) return st;
+    const HankelPlan &hp = dh->hp;
+    if (ws_bytes < hp.ws_bytes || ws == nullptr)
+        return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", hp.ws_bytes, ws_bytes);
+    HankelArgs ha{};
+    ha.A = static_cast<const float2 *>(A);
+    ha.lda = lda;
+    ha.N = N;
+    ha.M = M;
+    ha.P = P;
+    ha.Q = Q;
+    ha.PQ = P * Q;
+    ha.Kr = N - P + 1;
+    ha.Kc = M - Q + 1;
+    ha.pb = hp.pb;
+    ha.qb = hp.qb;
+    ha.stride_a = hp.stride_a;
+    ha.stride_b = hp.stride_b;
+    ha.items = dh->d_items;
+    ha.tiles = dh->d_tiles;
+    ha.partial = static_cast<double *>(ws);
+    ha.R = R;
+    ha.ldr = ldr;
+    ha.fill_full = o.fill == COVEST_FILL_FULL ? 1 : 0;
+    ha.normalize = o.normalize ? 1 : 0;
+    HIP_TRY(timed("hankel_main", stream, [&] {
+        return launch_hankel_main(ha, prec, (int)hp.items.size(), hp.lds, stream);
+    }));
+    HIP_TRY(timed("hankel_reduce", stream, [&] {
+        return launch_hankel_reduce(ha, (int)hp.tiles.size(), stream);
+    }));
+    return finish_call(stream);
+}
+
 }  // namespace
 
 // =================================================================== ABI ====
@@ -319,7 +425,12 @@ int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q, const cove
         *bytes = host_plan((int)N, (int)M, (int)P, (int)Q)->ws_bytes;
         return ok();
     }
-    return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form is not available in this build");
+    const int prec = hankel_prec(o.prec);
+    if (prec < 0) return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form has no FP64 precision");
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form supports P, Q <= %d", kMaxWindow);
+    *bytes = host_hankel_plan((int)N, (int)M, (int)P, (int)Q, prec)->ws_bytes;
+    return ok();
 }
 
 int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,
@@ -336,7 +447,7 @@ int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t 
     if (ldr < P * Q) return fail(COVEST_ERR_INVALID_ARG, "ldr (%lld) < PQ (%lld)", (long long)ldr, (long long)(P * Q));
     if (use_recurrence(o))
         return rec_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, ws, ws_bytes, stream);
-    return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form is not available in this build");
+    return hankel_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, ws, ws_bytes, stream);
 }
 
 int covest_forward(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,

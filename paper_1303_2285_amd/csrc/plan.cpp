@@ -228,9 +228,10 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
         sp.lds_main = std::max(sp.lds_main, tile_bytes(rows, tc + halo_c));
     }
 
-    // Finalize items: every unique combination (eq. 3.3).
-    for (int dc = 0; dc < Q; ++dc) {
-        for (int dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
+    // Finalize items: every unique combination (eq. 3.3), in lag-index order
+    // (dr-major) so that neighbouring items read neighbouring partial sums.
+    for (int dr = -(P - 1); dr < P; ++dr) {
+        for (int dc = (dr < 0 ? 1 : 0); dc < Q; ++dc) {
             FinItem it{};
             it.inst = 0;
             it.dr = dr;
@@ -247,7 +248,7 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
             sp.items.push_back(it);
         }
     }
-    const size_t table = (size_t)(1 + sp.n_ir) * sp.n_ic * 16;
+    const size_t table = (size_t)(1 + sp.n_ir) * (sp.n_ic | 1) * 16;
     sp.fin_table = table <= kFinTableMax;
     sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
 
@@ -272,6 +273,79 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
     sp.fin_products = corner;
     sp.main_products = cnt.um - corner;
     return sp;
+}
+
+}  // namespace covest
+
+namespace covest {
+
+static int planes_of(int prec)
+{
+    switch (prec) {
+    case kPrecF32: return 3;
+    case kPrecBF16: case kPrecF16: return 2;
+    default: return 4;
+    }
+}
+
+// Row stride of an LDS window: at least w, and 4 (mod 32) 4-byte elements so
+// that 16-byte reads of consecutive rows fall in different banks.
+static int pad_stride(int w) { return w + ((4 - w) % 32 + 32) % 32; }
+
+HankelPlan make_hankel_plan(int N, int M, int P, int Q, int prec, int n_cu)
+{
+    HankelPlan hp;
+    hp.N = N; hp.M = M; hp.P = P; hp.Q = Q; hp.prec = prec;
+    const int PQ = P * Q, Kr = N - P + 1, Kc = M - Q + 1;
+    const int nt = (PQ + 63) / 64;
+    const int npl = planes_of(prec);
+    // widest column window of a 64-row tile
+    int span = 0;
+    for (int t = 0; t < nt; ++t) {
+        const int lo = (64 * t) / P, hi = std::min(Q - 1, std::min(PQ - 1, 64 * t + 63) / P);
+        span = std::max(span, hi - lo);
+    }
+    // sub-tile: the most positions per staged byte within the LDS budget
+    const size_t budget = 76 * 1024;
+    double best = -1.0;
+    for (int qb : {32, 64, 128}) {
+        const int s = pad_stride(qb + span);
+        for (int pb = 1; pb <= std::max(1, Kr); ++pb) {
+            const size_t bytes = (size_t)npl * (pb + P) * (2 * s) * 4;
+            if (bytes > budget) break;
+            const double eff = (double)pb * qb / ((double)(pb + P) * s);
+            if (eff > best) {
+                best = eff;
+                hp.pb = pb;
+                hp.qb = qb;
+                hp.stride_a = hp.stride_b = s;
+                hp.lds = bytes;
+            }
+        }
+    }
+    if (hp.pb == 0) {   // very large windows: one row of positions, one workgroup per CU
+        hp.qb = 32;
+        hp.pb = 1;
+        hp.stride_a = hp.stride_b = pad_stride(32 + span);
+        hp.lds = (size_t)npl * (1 + P) * (2 * hp.stride_a) * 4;
+    }
+    // split the position rows of every upper tile so that there are ~8 items per CU
+    const int n_tiles = nt * (nt + 1) / 2;
+    const int target = 8 * std::max(1, n_cu);
+    int splits = std::max(1, std::min(Kr, (target + n_tiles - 1) / n_tiles));
+    for (int a = 0; a < nt; ++a) {
+        for (int b = a; b < nt; ++b) {
+            HTile t{64 * a, 64 * b, (int)hp.items.size(), 0};
+            for (int s = 0; s < splits; ++s) {
+                const int p0 = (int)((int64_t)s * Kr / splits), p1 = (int)((int64_t)(s + 1) * Kr / splits);
+                if (p1 > p0) hp.items.push_back({64 * a, 64 * b, p0, p1});
+            }
+            t.item1 = (int)hp.items.size();
+            hp.tiles.push_back(t);
+        }
+    }
+    hp.ws_bytes = hp.items.size() * (size_t)64 * 64 * 16;
+    return hp;
 }
 
 }  // namespace covest

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "covest_internal.hpp"
+#include "hankel_internal.hpp"
 
 namespace covest {
 
@@ -41,6 +42,19 @@ struct ShapePlan {
 
 // n_slots: workgroups resident at once on the target device (2 per CU).
 ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots);
+
+// Plan of the plain (matrix-core) form for one shape and precision.
+struct HankelPlan {
+    int N = 0, M = 0, P = 0, Q = 0, prec = 0;
+    int pb = 0, qb = 0, stride_a = 0, stride_b = 0;
+    std::vector<HItem> items;
+    std::vector<HTile> tiles;
+    size_t lds = 0;
+    size_t ws_bytes = 0;     // FP64 partial tiles
+};
+
+// n_cu: compute units of the device (work items are sized for ~8 per CU).
+HankelPlan make_hankel_plan(int N, int M, int P, int Q, int prec, int n_cu);
 
 // Limits of the recurrence form.
 constexpr int kMaxWindow = 64;           // P, Q <= kMaxWindow

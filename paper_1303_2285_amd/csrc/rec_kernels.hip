@@ -78,35 +78,35 @@ __device__ __forceinline__ void ring_walk(const double2 *__restrict__ xs,
 }
 
 // Stage B[tr0 + i][tc0 + j] (i < nr, j < nc) as FP64 into lds[i * stride + j];
-// B = A (orient 0) or A^T (orient 1); entries outside A are zero.
+// B = A (orient 0) or A^T (orient 1); entries outside A are zero.  The global
+// loads are issued in batches of kFillBatch per thread before any of them is
+// used, so their latencies overlap.
+constexpr int kFillBatch = 8;
+
 __device__ __forceinline__ void fill_tile(double2 *lds, int stride, const Inst &in, int orient,
                                           int tr0, int nr, int tc0, int nc)
 {
     const float2 *A = static_cast<const float2 *>(in.A);
     const int total = nr * nc;
-    if (orient == 0) {
-        for (int e = threadIdx.x; e < total; e += kThreads) {
-            const int i = e / nc, j = e - i * nc;
-            const int r = tr0 + i, c = tc0 + j;
-            double2 v = make_double2(0.0, 0.0);
-            if (r >= 0 && r < in.N && c >= 0 && c < in.M) {
-                const float2 a = A[(int64_t)r * in.lda + c];
-                v = make_double2((double)a.x, (double)a.y);
-            }
-            lds[i * stride + j] = v;
+    // orient 0: j (A column) runs fastest; orient 1: i (A column) runs fastest
+    const int fast = orient ? nr : nc;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kFillBatch * kThreads) {
+        float2 v[kFillBatch];
+        int dst[kFillBatch];
+#pragma unroll
+        for (int k = 0; k < kFillBatch; ++k) {
+            const int e = e0 + k * kThreads;
+            const int s = e / fast, f = e - s * fast;
+            const int i = orient ? f : s, j = orient ? s : f;
+            const int ar = orient ? tc0 + j : tr0 + i;
+            const int ac = orient ? tr0 + i : tc0 + j;
+            const bool ok = e < total && ar >= 0 && ar < in.N && ac >= 0 && ac < in.M;
+            v[k] = ok ? A[(int64_t)ar * in.lda + ac] : make_float2(0.f, 0.f);
+            dst[k] = e < total ? i * stride + j : -1;
         }
-    } else {
-        // i runs fastest so that consecutive threads read consecutive A columns
-        for (int e = threadIdx.x; e < total; e += kThreads) {
-            const int j = e / nr, i = e - j * nr;
-            const int ac = tr0 + i, ar = tc0 + j;
-            double2 v = make_double2(0.0, 0.0);
-            if (ar >= 0 && ar < in.N && ac >= 0 && ac < in.M) {
-                const float2 a = A[(int64_t)ar * in.lda + ac];
-                v = make_double2((double)a.x, (double)a.y);
-            }
-            lds[i * stride + j] = v;
-        }
+#pragma unroll
+        for (int k = 0; k < kFillBatch; ++k)
+            if (dst[k] >= 0) lds[dst[k]] = make_double2((double)v[k].x, (double)v[k].y);
     }
 }
 
@@ -218,13 +218,14 @@ __device__ void run_strip(const Job &job, const Inst &in, const LagGroup &g, dou
     }
 }
 
+// Workgroup b of a launch runs on XCD b % 8.  Map the workgroups of one XCD
+// to one contiguous range of the work list (any n), so that neighbouring work
+// items (jobs over one region of A, or finalize items of neighbouring lags,
+// whose partial sums share cache lines) meet in the same L2.
 __device__ __forceinline__ int xcd_block(int b, int n)
 {
-    // Workgroup b runs on XCD b % 8.  Give the workgroups of one XCD a
-    // contiguous range of jobs (jobs are generated in spatial order), so an
-    // XCD's L2 holds one region of A.
-    const int per = n / 8;
-    return (b % 8) * per + b / 8;
+    const int x = b & 7;
+    return x * (n >> 3) + min(x, n & 7) + (b >> 3);
 }
 
 __global__ void __launch_bounds__(kThreads, 2) rec_main(MainArgs ma)
@@ -290,7 +291,7 @@ __device__ __forceinline__ void store_r(const Inst &in, int k1, int k2, double2 
 __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
 {
     extern __shared__ double2 cs[];
-    const FinItem it = fa.items[blockIdx.x];
+    const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
     const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
     const int P = in.P, N = in.N, Kr = in.Kr, Kc = in.Kc;
     const int dr = it.dr, dc = it.dc;
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 {
     extern __shared__ double2 V[];
     __shared__ double2 red[256];
-    const FinItem it = fa.items[blockIdx.x];
+    const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
     const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
     const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
     const int dr = it.dr, dc = it.dc;
@@ -397,6 +398,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
     const float2 *A = static_cast<const float2 *>(in.A);
     const int nV = in.n_ic;
+    const int nVs = nV | 1;   // odd row stride: no LDS bank conflicts across rows
     const int ncls = 1 + in.n_ir;
 
     // Middle sum: fixed-order tree over the bulk partials.
@@ -428,48 +430,72 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
                 }
             }
         }
-        V[e] = v;
+        V[cls * nVs + gi] = v;
     }
     __syncthreads();
 
-    // Phase B: per class, the sums over the column range of every offset b,
-    // written in place over the (already consumed) left-column terms.
-    for (int cls = tid; cls < ncls; cls += 256) {
-        double2 s;
-        if (cls == 0) {
-            s = has_mr ? zm : make_double2(0.0, 0.0);
-        } else {
+    // Phase B: per class, the sums over the column range of every offset b.
+    // Thread (class, chunk of kFinChunk offsets) seeds its first offset with a
+    // direct sum and slides across the chunk (one column leaves, one enters);
+    // results are written in place over the consumed left-column terms after
+    // a barrier.
+    constexpr int kFinChunk = 8;
+    const int nchunk_b = (nc + kFinChunk - 1) / kFinChunk;
+    const int cls_per = 256 / nchunk_b;   // whole classes per pass: a class is never split
+    for (int cbase = 0; cbase < ncls; cbase += cls_per) {
+        const int cls = cbase + tid / nchunk_b, ch = tid % nchunk_b;
+        double2 res[kFinChunk];
+        bool live = tid < cls_per * nchunk_b && cls < ncls;
+        if (live && cls > 0) {
             const int rho = cls - 1;
             const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
-            if (r < rlo || r >= rhi) continue;
-            s = has_mc ? zr[rho * ls2 + lag] : make_double2(0.0, 0.0);
+            live = r >= rlo && r < rhi;
         }
-        double2 *row = V + cls * nV;
-        for (int gi = 0; gi < min(Cm0, Kc); ++gi) s = cadd(s, row[gi]);
-        for (int c = Cm1; c < Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);
-        for (int b = 0; b + 1 < nc; ++b) {
-            const double2 vo = row[b];
-            const double2 vi = row[Cm0 + (b + Kc) - Cm1];
-            row[b] = s;
-            s = cadd(csub(s, vo), vi);
+        const int b0 = ch * kFinChunk, b1 = min(nc, b0 + kFinChunk);
+        if (live) {
+            const double2 *row = V + cls * nVs;
+            double2 s;
+            if (cls == 0) s = has_mr ? zm : make_double2(0.0, 0.0);
+            else s = has_mc ? zr[(cls - 1) * ls2 + lag] : make_double2(0.0, 0.0);
+            // columns [b0, b0 + Kc) of the individual set: left part, right part
+            for (int gi = b0; gi < min(Cm0, b0 + Kc); ++gi) s = cadd(s, row[gi]);
+            for (int c = max(Cm1, b0); c < b0 + Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);
+#pragma unroll
+            for (int k = 0; k < kFinChunk; ++k) {
+                const int b = b0 + k;
+                res[k] = s;
+                if (b + 1 < b1) s = cadd(csub(s, row[b]), row[Cm0 + (b + Kc) - Cm1]);
+            }
         }
-        row[nc - 1] = s;
+        __syncthreads();
+        if (live) {
+            double2 *row = V + cls * nVs;
+#pragma unroll
+            for (int k = 0; k < kFinChunk; ++k)
+                if (b0 + k < b1) row[b0 + k] = res[k];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
-    // Phase C: for each column offset b, slide the box down the segment.
-    for (int b = tid; b < nc; b += 256) {
+    // Phase C: thread (b, chunk of kFinChunk row offsets) seeds the box at its
+    // first offset with a direct sum over the row classes and slides it down
+    // the segment (one row leaves, one enters), writing each entry.
+    const int nchunk_a = (nr + kFinChunk - 1) / kFinChunk;
+    for (int t = tid; t < nc * nchunk_a; t += 256) {
+        const int b = t % nc, ch = t / nc;
+        const int a0 = ch * kFinChunk, a1 = min(nr, a0 + kFinChunk);
+        const int i0 = rlo + a0;
         double2 s = V[b];
-        for (int r = rlo; r < min(Rm0, rlo + Kr); ++r) s = cadd(s, V[(1 + r) * nV + b]);
-        for (int r = max(Rm1, rlo); r < rlo + Kr; ++r) s = cadd(s, V[(1 + Rm0 + r - Rm1) * nV + b]);
-        for (int a = 0; a < nr; ++a) {
+        for (int r = i0; r < min(Rm0, i0 + Kr); ++r) s = cadd(s, V[(1 + r) * nVs + b]);
+        for (int r = max(Rm1, i0); r < i0 + Kr; ++r) s = cadd(s, V[(1 + Rm0 + r - Rm1) * nVs + b]);
+        for (int a = a0; a < a1; ++a) {
             const int i1 = rlo + a;
             const int k1 = i1 + P * b;
             const int k2 = (i1 + dr) + P * (b + dc);
             store_r(in, k1, k2, s, dr == 0 && dc == 0);
-            if (a + 1 < nr) {
-                s = csub(s, V[(1 + i1) * nV + b]);
-                s = cadd(s, V[(1 + Rm0 + i1 + Kr - Rm1) * nV + b]);
+            if (a + 1 < a1) {
+                s = csub(s, V[(1 + i1) * nVs + b]);
+                s = cadd(s, V[(1 + Rm0 + i1 + Kr - Rm1) * nVs + b]);
             }
         }
     }
