@@ -29,6 +29,9 @@ if ROOT not in sys.path:
 METRIC = ("R matrices/s + GFLOP/s, 1024² A, 32×32 window: chosen vs plain form "
           "at rel err ≤1e-5")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 64 FP64 FMA lanes x 2 flops
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense, per the datasheet
+PLAIN_FORMS = [("fp32", 1, "fp32"), ("bf16x3", 3, "bf16"), ("fp16x3", 3, "fp16"),
+               ("fp16", 1, "fp16"), ("bf16", 1, "bf16")]   # (precision, passes, peak key)
 N, M, P, Q = 1024, 1024, 32, 32
 
 
@@ -39,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
+    ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
     return ap.parse_args()
 
 
@@ -134,6 +139,49 @@ def main():
     scale = np.abs(np.diag(R_h)).max()
     sampled_err = float(np.abs(R_h[k1, k2] - ref).max() / scale)
 
+    # The plain form (eq. 2.2 as a dense product on the matrix cores), same input.
+    sample_k1 = np.concatenate([np.arange(0, P * Q, 8), k1])
+    sample_k2 = np.concatenate([np.arange(0, P * Q, 8), k2])
+    ref_s = oracle.entries(A_np, P, Q, sample_k1, sample_k2, threads=oracle.max_threads())
+
+    def sampled_rel(Rm):
+        got = Rm[sample_k1, sample_k2].astype(np.complex128)
+        return float(np.linalg.norm(got - ref_s) / np.linalg.norm(ref_s))
+
+    chosen_rel = sampled_rel(R_h)
+    plain = {}
+    if not args.no_plain:
+        for prec, passes, peak_key in PLAIN_FORMS:
+            need = covest.workspace_size(N, M, P, Q, form="hankel", precision=prec)
+            wsp = torch.empty(need, dtype=torch.uint8, device=dev)
+            Rp = torch.empty((P * Q, P * Q), dtype=torch.complex64, device=dev)
+            run = lambda: covest.covest_forward(A, P, Q, form="hankel", precision=prec, out=Rp,
+                                                workspace=wsp)
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                run()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.plain_steps
+            covest.timing_reset()
+            covest.timing_enable(True)
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            rk = covest.timing_read()
+            covest.timing_enable(False)
+            kms = rk["hankel_main"][1] / rk["hankel_main"][0]
+            f_mfma = passes * 8.0 * cnt["K"] * cnt["eta"]
+            plain[prec] = {"ms_per_matrix": ms, "matrices_per_s": 1e3 / ms,
+                           "rel_err_sampled": sampled_rel(Rp.cpu().numpy()),
+                           "hankel_main_ms": kms,
+                           "mfma_tflops": f_mfma / (kms * 1e-3) / 1e12,
+                           "mfma_frac": f_mfma / (kms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[peak_key]}
+            print(f"[bench] plain {prec}: {ms:.3f} ms/matrix, rel err {plain[prec]['rel_err_sampled']:.2e}",
+                  file=sys.stderr, flush=True)
+            del wsp, Rp
+
     f_nom = 8.0 * cnt["K"] * cnt["eta"]         # plain-form flops: every product recomputed
     f_alg = 8.0 * cnt["um"]                     # each distinct product once
     out = {
@@ -156,7 +204,11 @@ def main():
         "gflops_algorithmic": f_alg / (ms_per_step * 1e-3) / 1e9,
         "kernels_ms": {"rec_main": main_avg_ms, "rec_finalize": fin_avg_ms},
         "rel_err_sampled_max": sampled_err,
-        "plain_form": None,
+        "rel_err_sampled": chosen_rel,
+        "plain_form": ({"form": "hankel_mfma", "precision": "fp32", **plain["fp32"]}
+                       if "fp32" in plain else None),
+        "speedup_vs_plain_fp32": (value / plain["fp32"]["matrices_per_s"]) if "fp32" in plain else None,
+        "other_forms": {k: v for k, v in plain.items() if k != "fp32"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None},

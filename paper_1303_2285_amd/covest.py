@@ -295,6 +295,45 @@ def covest_forward_batched(plan: BatchedPlan):
     return plan.run()
 
 
+def _make_autograd():
+    import torch
+
+    class CovEst(torch.autograd.Function):
+        """R = covest_forward(A, P, Q) with the hand-written adjoint as backward.
+
+        The forward returns the full Hermitian R (complex128 for precision
+        "fp64").  The backward receives dL/dR in PyTorch's convention and returns
+        dL/dA = fold((dR + dR^H) X) / K from covest_backward (complex64).
+        """
+
+        @staticmethod
+        def forward(ctx, A, P, Q, precision="fp64", normalize=True):
+            R = covest_forward(A.detach(), P, Q, precision=precision, fill="full", normalize=normalize)
+            ctx.save_for_backward(A)
+            ctx.P, ctx.Q, ctx.normalize = int(P), int(Q), bool(normalize)
+            return R
+
+        @staticmethod
+        def backward(ctx, gR):
+            (A,) = ctx.saved_tensors
+            dA = covest_backward(A.detach(), gR.to(torch.complex64).contiguous(), ctx.P, ctx.Q,
+                                 normalize=ctx.normalize)
+            return dA, None, None, None, None
+
+    return CovEst
+
+
+_covest_fn = None
+
+
+def covest_apply(A, P, Q, precision="fp64", normalize=True):
+    """Differentiable forward: CovEst.apply(A, P, Q, precision, normalize)."""
+    global _covest_fn
+    if _covest_fn is None:
+        _covest_fn = _make_autograd()
+    return _covest_fn.apply(A, P, Q, precision, normalize)
+
+
 # ---------------------------------------------------------------- timing ----
 
 def timing_enable(on: bool = True):

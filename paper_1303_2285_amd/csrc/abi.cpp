@@ -5,6 +5,7 @@
 // arithmetic of the method happens here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -18,6 +19,7 @@
 
 #include "covest.h"
 #include "covest_plan.h"
+#include "adj_internal.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -387,6 +389,41 @@ int hankel_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void 
     return finish_call(stream);
 }
 
+// --------------------------------------------------------------- adjoint ----
+struct AdjGeom {
+    int ir0, ir1, ic0, ic1, ndc, n_lags, interior_blocks;
+    int64_t n_frame;
+    size_t lds_tables, lds_interior, ws_bytes;
+};
+
+AdjGeom adj_geometry(int N, int M, int P, int Q)
+{
+    AdjGeom g{};
+    const int Kr = N - P + 1, Kc = M - Q + 1;
+    g.n_lags = (2 * P - 1) * (2 * Q - 1);
+    g.ndc = ((2 * Q - 1 + 15) / 16) * 16;
+    g.lds_tables = (size_t)(P + 1) * (Q + 1) * 16;
+    const int rows = kAdjTR + 2 * (P - 1);
+    const int stride = (kAdjTC + g.ndc) | 1;
+    g.lds_interior = std::max((size_t)(2 * P - 1) * g.ndc * 16 + (size_t)rows * stride * 8,
+                              (size_t)256 * 16 * 16);
+    const bool interior = Kr > P - 1 && Kc > Q - 1 && g.lds_interior <= 150 * 1024;
+    if (interior) {
+        g.ir0 = P - 1;
+        g.ir1 = Kr;
+        g.ic0 = Q - 1;
+        g.ic1 = Kc;
+        g.interior_blocks = ((g.ir1 - g.ir0 + kAdjTR - 1) / kAdjTR) * ((g.ic1 - g.ic0 + kAdjTC - 1) / kAdjTC);
+    } else {
+        g.ir0 = g.ir1 = N;   // no interior: the frame is every output
+        g.ic0 = g.ic1 = 0;
+        g.interior_blocks = 0;
+    }
+    g.n_frame = (int64_t)N * M - (int64_t)(g.ir1 - g.ir0) * (g.ic1 - g.ic0);
+    g.ws_bytes = (size_t)g.n_lags * (P + 1) * (Q + 1) * 16 + (size_t)g.n_lags * 16;
+    return g;
+}
+
 }  // namespace
 
 // =================================================================== ABI ====
@@ -459,17 +496,59 @@ int covest_forward(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, vo
 int covest_backward_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,
                                    const covest_opts *opts, size_t *bytes)
 {
-    (void)N; (void)M; (void)P; (void)Q; (void)opts;
     if (!bytes) return fail(COVEST_ERR_INVALID_ARG, "bytes is null");
-    return fail(COVEST_ERR_UNSUPPORTED, "the adjoint is not available in this build");
+    const covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the adjoint supports P, Q <= %d", kMaxWindow);
+    *bytes = adj_geometry((int)N, (int)M, (int)P, (int)Q).ws_bytes;
+    return ok();
 }
 
 int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t M, int64_t P, int64_t Q,
                     const covest_opts *opts, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    (void)A; (void)dR; (void)dA; (void)N; (void)M; (void)P; (void)Q; (void)opts; (void)ws;
-    (void)ws_bytes; (void)stream;
-    return fail(COVEST_ERR_UNSUPPORTED, "the adjoint is not available in this build");
+    const covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (!A || !dR || !dA) return fail(COVEST_ERR_INVALID_ARG, "A, dR and dA must be non-null device pointers");
+    if (dA == A || dA == dR) return fail(COVEST_ERR_INVALID_ARG, "dA must not alias A or dR");
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the adjoint supports P, Q <= %d", kMaxWindow);
+    const AdjGeom g = adj_geometry((int)N, (int)M, (int)P, (int)Q);
+    if (ws_bytes < g.ws_bytes || ws == nullptr)
+        return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.ws_bytes, ws_bytes);
+    AdjArgs aa{};
+    aa.A = static_cast<const float2 *>(A);
+    aa.lda = M;
+    aa.G = static_cast<const float2 *>(dR);
+    aa.ldg = P * Q;
+    aa.dA = static_cast<float2 *>(dA);
+    aa.ldda = M;
+    aa.N = (int)N;
+    aa.M = (int)M;
+    aa.P = (int)P;
+    aa.Q = (int)Q;
+    aa.Kr = (int)(N - P + 1);
+    aa.Kc = (int)(M - Q + 1);
+    aa.ir0 = g.ir0;
+    aa.ir1 = g.ir1;
+    aa.ic0 = g.ic0;
+    aa.ic1 = g.ic1;
+    aa.ndc = g.ndc;
+    aa.n_frame = g.n_frame;
+    aa.tables = static_cast<double *>(ws);
+    aa.hfull = aa.tables + (size_t)2 * g.n_lags * (P + 1) * (Q + 1);
+    aa.normalize = o.normalize ? 1 : 0;
+    HIP_TRY(timed("adjoint", stream, [&] {
+        return launch_adjoint(aa, g.n_lags, g.lds_tables, g.interior_blocks, g.lds_interior, g.n_frame, stream);
+    }));
+    return finish_call(stream);
 }
 
 int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,

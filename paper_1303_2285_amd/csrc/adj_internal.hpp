@@ -1,0 +1,33 @@
+// adj_internal.hpp -- types shared by the host and the adjoint kernels.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace covest {
+
+constexpr int kAdjTR = 16;   // interior outputs per workgroup: rows
+constexpr int kAdjTC = 64;   // interior outputs per workgroup: columns (16 per thread)
+
+struct AdjArgs {
+    const float2 *A;
+    int64_t lda;
+    const float2 *G;            // dL/dR, PQ x PQ complex64
+    int64_t ldg;
+    float2 *dA;
+    int64_t ldda;
+    int N, M, P, Q, Kr, Kc;
+    int ir0, ir1, ic0, ic1;     // interior outputs [ir0, ir1) x [ic0, ic1)
+    int ndc;                    // 2Q-1 rounded up to a multiple of 16
+    int64_t n_frame;            // outputs outside the interior
+    double *tables;             // [(2P-1)(2Q-1)][(P+1)(Q+1)] complex FP64 prefix sums
+    double *hfull;              // [(2P-1)(2Q-1)] complex FP64 full sums
+    int normalize;
+    int pad;
+};
+
+hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int n_interior_blocks,
+                          size_t lds_interior, int64_t n_frame, hipStream_t s);
+
+}  // namespace covest

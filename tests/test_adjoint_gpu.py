@@ -1,0 +1,176 @@
+"""GPU adjoint (covest_backward) and the autograd path.
+
+* against the oracle's adjoint: direct loops on small shapes (random,
+  non-Hermitian G) and the BLAS fold(H X)/K route at 512 x 512, 16 x 16;
+* the bilinearity dot-product test (exact first-order change, no step size);
+* FP64 central differences with Richardson extrapolation on the workload's
+  loss L = Re tr(W R) + ||R - R_t||_F^2, which is quartic in every real
+  coordinate of A, so the extrapolated difference has no truncation error.
+  A is quantised to multiples of 2^-16 there so that every perturbed input is
+  exactly representable in complex64.
+The dA output is complex64 (FP64 inside): bars are relative errors 1e-6
+(the workload's 1e-4 for the adjoint, 1e-6 for the differences).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1303_2285_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tdev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cv():
+    from paper_1303_2285_amd import covest
+    covest.lib()
+    return covest
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+SMALL = [(9, 11, 3, 4), (12, 10, 5, 2), (7, 7, 7, 7), (8, 13, 1, 6), (20, 18, 4, 4), (40, 33, 8, 5),
+         (64, 64, 8, 8), (70, 50, 16, 12)]
+
+
+@pytest.mark.parametrize("shape", SMALL, ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_vs_oracle_small(cv, tdev, oracle_mod, shape):
+    torch, dev = tdev
+    N, M, P, Q = shape
+    rng = np.random.default_rng(N * 100 + M)
+    A = synth.gaussian(N, M, seed=N + 3 * M)
+    G = (rng.standard_normal((P * Q, P * Q)) + 1j * rng.standard_normal((P * Q, P * Q))).astype(np.complex64)
+    _note("adjoint small", shape)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q)
+    torch.cuda.synchronize()
+    ref = oracle_mod.adjoint(A, G, P, Q)
+    assert rel(dA.cpu().numpy().astype(np.complex128), ref) <= 1e-6
+
+
+def test_adjoint_unnormalized(cv, tdev, oracle_mod):
+    torch, dev = tdev
+    A = synth.gaussian(15, 17, seed=2)
+    rng = np.random.default_rng(3)
+    G = (rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))).astype(np.complex64)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), 4, 3, normalize=False)
+    torch.cuda.synchronize()
+    ref = oracle_mod.adjoint(A, G, 4, 3, normalize=False)
+    assert rel(dA.cpu().numpy().astype(np.complex128), ref) <= 1e-6
+
+
+def workload(oracle_mod):
+    A, W, At = synth.adjoint_inputs()
+    P, Q = 16, 16
+    Rt = oracle_mod.forward_blas(At, P, Q)
+    return A, W, Rt, P, Q
+
+
+def test_workload_adjoint_vs_oracle(cv, tdev, oracle_mod):
+    """512 x 512, 16 x 16: dL/dA through CovEst.apply + autograd vs the oracle."""
+    torch, dev = tdev
+    A, W, Rt, P, Q = workload(oracle_mod)
+    _note("adjoint workload autograd")
+    At = torch.from_numpy(A).to(dev).requires_grad_(True)
+    Wt = torch.from_numpy(W).to(dev)
+    Rtt = torch.from_numpy(Rt).to(dev)
+    R = cv.covest_apply(At, P, Q)
+    L = (Wt * R.transpose(0, 1)).sum().real + ((R - Rtt).abs() ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    got = At.grad.cpu().numpy().astype(np.complex128)
+    Rh = oracle_mod.forward_blas(A, P, Q)
+    G = W + 2.0 * (Rh - Rt)             # dL/dR for Hermitian W
+    ref = oracle_mod.adjoint_blas(A, G, P, Q)
+    assert rel(got, ref) <= 1e-6
+
+
+def test_dot_product(cv, tdev, oracle_mod):
+    torch, dev = tdev
+    N, M, P, Q = 96, 80, 8, 6
+    A = synth.gaussian(N, M, seed=31)
+    d = synth.gaussian(N, M, seed=32)
+    rng = np.random.default_rng(33)
+    G = (rng.standard_normal((P * Q, P * Q)) + 1j * rng.standard_normal((P * Q, P * Q))).astype(np.complex64)
+    f = lambda X: cv.covest_forward(torch.from_numpy(X).to(dev), P, Q).cpu().numpy()
+    # A + d is formed in complex64 on both sides; bilinearity needs the exact sum
+    Apd = (A.astype(np.complex128) + d.astype(np.complex128)).astype(np.complex64)
+    dd = (Apd.astype(np.complex128) - A.astype(np.complex128))
+    dR = f(Apd) - f(A) - cv.covest_forward(torch.from_numpy(dd.astype(np.complex64)).to(dev), P, Q).cpu().numpy()
+    torch.cuda.synchronize()
+    lhs = np.real(np.vdot(G.astype(np.complex128), dR))
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q).cpu().numpy()
+    rhs = np.real(np.vdot(dA.astype(np.complex128), dd))
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+def _fd_block(cv, tdev, oracle_mod, r0, c0, size=32):
+    torch, dev = tdev
+    A, W, Rt, P, Q = workload(oracle_mod)
+    A = (np.round(A.astype(np.complex128) * 2 ** 16) / 2 ** 16).astype(np.complex64)
+    Ad = torch.from_numpy(A).to(dev)
+    Wt = torch.from_numpy(W).to(dev)
+    Rtt = torch.from_numpy(Rt).to(dev)
+    ws = torch.empty(cv.workspace_size(512, 512, P, Q), dtype=torch.uint8, device=dev)
+    R = torch.empty((P * Q, P * Q), dtype=torch.complex128, device=dev)
+
+    def loss():
+        cv.covest_forward(Ad, P, Q, out=R, workspace=ws)
+        return (Wt * R.transpose(0, 1)).sum().real + ((R - Rtt).abs() ** 2).sum()
+
+    h = 2.0 ** -6
+    fd = np.zeros((size, size), dtype=np.complex128)
+    for i in range(size):
+        for j in range(size):
+            for part, unit in ((0, 1.0), (1, 1j)):
+                vals = []
+                for s in (h, -h, 2 * h, -2 * h):
+                    Ad[r0 + i, c0 + j] = complex(A[r0 + i, c0 + j]) + s * unit
+                    vals.append(loss())
+                Ad[r0 + i, c0 + j] = complex(A[r0 + i, c0 + j])
+                v = torch.stack(vals).cpu().numpy()
+                d1 = (v[0] - v[1]) / (2 * h)
+                d2 = (v[2] - v[3]) / (4 * h)
+                g = (4 * d1 - d2) / 3
+                fd[i, j] += g if part == 0 else 1j * g
+    # analytic gradient through the adjoint
+    Ag = torch.from_numpy(A).to(dev).requires_grad_(True)
+    Rg = cv.covest_apply(Ag, P, Q)
+    L = (Wt * Rg.transpose(0, 1)).sum().real + ((Rg - Rtt).abs() ** 2).sum()
+    L.backward()
+    got = Ag.grad.cpu().numpy()[r0:r0 + size, c0:c0 + size].astype(np.complex128)
+    return rel(got, fd)
+
+
+def test_fd_interior_block(cv, tdev, oracle_mod):
+    _note("fd interior block [240,272)")
+    assert _fd_block(cv, tdev, oracle_mod, 240, 240) <= 1e-6
+
+
+def test_fd_corner_block(cv, tdev, oracle_mod):
+    _note("fd corner block [0,32)")
+    assert _fd_block(cv, tdev, oracle_mod, 0, 0) <= 1e-6
+
+
+def test_backward_errors(cv, tdev):
+    torch, dev = tdev
+    A = torch.zeros((8, 8), dtype=torch.complex64, device=dev)
+    with pytest.raises(ValueError):
+        cv.covest_backward(A, torch.zeros((9, 9), dtype=torch.complex64, device=dev), 4, 4)
+    with pytest.raises(cv.CovestError) as e:
+        cv.covest_backward(A, torch.zeros((81, 81), dtype=torch.complex64, device=dev), 9, 9)
+    assert e.value.status == cv.ERR_SHAPE
