@@ -78,6 +78,8 @@ typedef struct {
     covest_precision prec;
     covest_fill fill;
     int normalize;          /* 1: R = C / K (default); 0: the paper's unnormalised C       */
+    int ring_cols;          /* recurrence tile shape: lags per lane along columns (dc) and  */
+    int ring_rows;          /* along rows (dr): 4, 8, 12 or 16; 0 = the library's choice    */
 } covest_opts;
 
 /* Work counts of the method for one shape (Sec. 3.2-4.1):

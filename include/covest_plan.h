@@ -11,7 +11,9 @@
  * (Sec. 4.2-4.3).
  *
  * n_slots is the number of workgroups the plan assumes resident at once (two
- * per compute unit: 512 on MI355X).  All arrays are caller-owned host memory.
+ * per compute unit: 512 on MI355X).  w0 and w1 choose the ring widths (lags
+ * per lane along columns and along rows: 4, 8, 12 or 16; 0 = the default the
+ * library uses without tuning).  All arrays are caller-owned host memory.
  */
 #ifndef COVEST_PLAN_H
 #define COVEST_PLAN_H
@@ -40,10 +42,11 @@ typedef struct {
  * tile_rows, tile_cols).  Group rows: 14 int32 each (orient, W, d1lo, d1hi,
  * ch0, nch, v2lo, v2hi, lanes, slots, hr_lo, hr_hi, hc_lo, hc_hi).  Item rows:
  * 5 int32 each (inst, dr, dc, bulk0, bulk1).  COVEST_ERR_SHAPE on a bad shape,
- * COVEST_ERR_UNSUPPORTED when P or Q exceeds the recurrence's limit. */
-int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots,
-                         covest_plan_info *out);
-int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots,
+ * COVEST_ERR_UNSUPPORTED when P or Q exceeds the recurrence's limit,
+ * COVEST_ERR_INVALID_ARG for a width other than 0, 4, 8, 12 or 16. */
+int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t w0,
+                         int32_t w1, covest_plan_info *out);
+int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t w0, int32_t w1,
                        int32_t *jobs, int32_t *groups, int32_t *items);
 
 #ifdef __cplusplus

@@ -38,7 +38,7 @@ class CovestError(RuntimeError):
 
 class covest_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("prec", ctypes.c_int), ("fill", ctypes.c_int),
-                ("normalize", ctypes.c_int)]
+                ("normalize", ctypes.c_int), ("ring_cols", ctypes.c_int), ("ring_rows", ctypes.c_int)]
 
 
 class covest_counts_t(ctypes.Structure):
@@ -90,10 +90,10 @@ SIGNATURES = {
     "covest_last_error": (ctypes.c_char_p, []),
     "covest_version": (_int, []),
     # include/covest_plan.h
-    "covest_plan_info_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
-                                    ctypes.POINTER(covest_plan_info)]),
-    "covest_plan_tables": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_void_p,
-                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "covest_plan_info_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.POINTER(covest_plan_info)]),
+    "covest_plan_tables": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -124,12 +124,15 @@ def _check(status: int):
         raise CovestError(status, msg)
 
 
-def make_opts(form="auto", precision="fp64", fill="full", normalize=True) -> covest_opts:
+def make_opts(form="auto", precision="fp64", fill="full", normalize=True, ring_cols=0,
+              ring_rows=0) -> covest_opts:
     o = covest_opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.prec = PRECS[precision] if isinstance(precision, str) else int(precision)
     o.fill = FILLS[fill] if isinstance(fill, str) else int(fill)
     o.normalize = 1 if normalize else 0
+    o.ring_cols = int(ring_cols)
+    o.ring_rows = int(ring_rows)
     return o
 
 
@@ -190,7 +193,7 @@ def _workspace(nbytes: int, device):
 
 
 def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="full",
-                   normalize=True, out=None, workspace=None):
+                   normalize=True, out=None, workspace=None, ring_cols=0, ring_rows=0):
     """R = (1/K) sum_{p,q} V^{p,q} (V^{p,q})^H for the complex64 N x M tensor A.
 
     Returns a PQ x PQ tensor (complex128 for precision "fp64", complex64
@@ -199,7 +202,7 @@ def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="fu
     torch = _torch()
     _check_input(A)
     N, M = A.shape
-    o = make_opts(form, precision, fill, normalize)
+    o = make_opts(form, precision, fill, normalize, ring_cols, ring_rows)
     PQ = P * Q
     rdtype = torch.complex128 if o.prec == 0 else torch.complex64
     if out is None:
@@ -211,7 +214,7 @@ def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="fu
         if R.dtype != rdtype or R.shape != (PQ, PQ) or R.stride(1) != 1:
             raise ValueError("out has the wrong dtype, shape or layout")
     need = workspace_size(N, M, P, Q, form=form, precision=precision, fill=fill,
-                          normalize=normalize)
+                          normalize=normalize, ring_cols=ring_cols, ring_rows=ring_rows)
     if workspace is None or workspace.numel() < need:
         ws, nbytes = _workspace(need, A.device)
     else:
@@ -252,10 +255,11 @@ class _Problem:
 class BatchedPlan:
     """Many (A, P, Q) problems computed by one graph launch (covest_forward_batched)."""
 
-    def __init__(self, problems, precision="fp64", fill="full", normalize=True):
+    def __init__(self, problems, precision="fp64", fill="full", normalize=True, ring_cols=0,
+                 ring_rows=0):
         torch = _torch()
         self._problems = [_Problem(A, int(P), int(Q)) for (A, P, Q) in problems]
-        o = make_opts("recurrence", precision, fill, normalize)
+        o = make_opts("recurrence", precision, fill, normalize, ring_cols, ring_rows)
         rdtype = torch.complex128 if o.prec == 0 else torch.complex64
         arr = (covest_problem * len(self._problems))()
         self.outputs = []
@@ -353,22 +357,22 @@ def timing_read() -> dict:
             for i in range(min(n, 64))}
 
 
-def plan_info(N, M, P, Q, n_slots=512) -> dict:
+def plan_info(N, M, P, Q, n_slots=512, w0=0, w1=0) -> dict:
     """The recurrence plan's geometry for one shape (host only)."""
     info = covest_plan_info()
-    _check(lib().covest_plan_info_get(N, M, P, Q, n_slots, ctypes.byref(info)))
+    _check(lib().covest_plan_info_get(N, M, P, Q, n_slots, w0, w1, ctypes.byref(info)))
     return {name: getattr(info, name) for name, _ in covest_plan_info._fields_}
 
 
-def plan_tables(N, M, P, Q, n_slots=512):
+def plan_tables(N, M, P, Q, n_slots=512, w0=0, w1=0):
     """(jobs[n,12], groups[n,14], items[n,5]) int32 arrays of the recurrence plan."""
     import numpy as np
-    info = plan_info(N, M, P, Q, n_slots)
+    info = plan_info(N, M, P, Q, n_slots, w0, w1)
     jobs = np.zeros((info["n_jobs"], 12), dtype=np.int32)
     groups = np.zeros((info["n_groups"], 14), dtype=np.int32)
     items = np.zeros((info["n_items"], 5), dtype=np.int32)
-    _check(lib().covest_plan_tables(N, M, P, Q, n_slots, jobs.ctypes.data, groups.ctypes.data,
-                                    items.ctypes.data))
+    _check(lib().covest_plan_tables(N, M, P, Q, n_slots, w0, w1, jobs.ctypes.data,
+                                    groups.ctypes.data, items.ctypes.data))
     return info, jobs, groups, items
 
 

@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -102,6 +104,7 @@ covest_opts resolve_opts(const covest_opts *o)
     r.prec = COVEST_PREC_FP64;
     r.fill = COVEST_FILL_FULL;
     r.normalize = 1;
+    r.ring_cols = r.ring_rows = 0;
     if (o) r = *o;
     return r;
 }
@@ -114,6 +117,9 @@ int check_opts(const covest_opts &o)
         return fail(COVEST_ERR_INVALID_ARG, "unknown precision %d", (int)o.prec);
     if (o.fill != COVEST_FILL_FULL && o.fill != COVEST_FILL_UPPER)
         return fail(COVEST_ERR_INVALID_ARG, "unknown fill %d", (int)o.fill);
+    for (int w : {o.ring_cols, o.ring_rows})
+        if (w != 0 && w != 4 && w != 8 && w != 12 && w != 16)
+            return fail(COVEST_ERR_INVALID_ARG, "ring widths are 0, 4, 8, 12 or 16 (got %d)", w);
     return COVEST_OK;
 }
 
@@ -142,7 +148,7 @@ struct DevPlan {
 };
 
 std::mutex g_pmu;
-std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<DevPlan>> g_plans;
+std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<DevPlan>> g_plans;
 
 int n_slots_for_device(int dev)
 {
@@ -162,11 +168,11 @@ hipError_t upload(T **dst, const std::vector<T> &src)
     return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
-int get_plan(int N, int M, int P, int Q, DevPlan **out)
+int get_plan(int N, int M, int P, int Q, int w0, int w1, DevPlan **out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    auto key = std::make_tuple(dev, N, M, P, Q);
+    auto key = std::make_tuple(dev, N, M, P, Q, w0, w1);
     std::lock_guard<std::mutex> lk(g_pmu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
@@ -174,7 +180,7 @@ int get_plan(int N, int M, int P, int Q, DevPlan **out)
         return COVEST_OK;
     }
     auto dp = std::make_unique<DevPlan>();
-    dp->sp = make_shape_plan(N, M, P, Q, n_slots_for_device(dev));
+    dp->sp = make_shape_plan(N, M, P, Q, n_slots_for_device(dev), w0, w1);
     HIP_TRY(upload(&dp->d_jobs, dp->sp.jobs));
     HIP_TRY(upload(&dp->d_groups, dp->sp.groups));
     HIP_TRY(upload(&dp->d_items, dp->sp.items));
@@ -185,18 +191,18 @@ int get_plan(int N, int M, int P, int Q, DevPlan **out)
 }
 
 std::mutex g_hmu;
-std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<const ShapePlan>> g_host_plans;
+std::map<std::tuple<int, int, int, int, int, int, int>, std::shared_ptr<const ShapePlan>> g_host_plans;
 
 // Host-only planning, cached (workspace queries must work without a device).
-std::shared_ptr<const ShapePlan> host_plan(int N, int M, int P, int Q)
+std::shared_ptr<const ShapePlan> host_plan(int N, int M, int P, int Q, int w0, int w1)
 {
     int dev = 0, slots = 512;
     if (hipGetDevice(&dev) == hipSuccess) slots = n_slots_for_device(dev);
-    auto key = std::make_tuple(slots, N, M, P, Q);
+    auto key = std::make_tuple(slots, N, M, P, Q, w0, w1);
     std::lock_guard<std::mutex> lk(g_hmu);
     auto it = g_host_plans.find(key);
     if (it != g_host_plans.end()) return it->second;
-    auto sp = std::make_shared<const ShapePlan>(make_shape_plan(N, M, P, Q, slots));
+    auto sp = std::make_shared<const ShapePlan>(make_shape_plan(N, M, P, Q, slots, w0, w1));
     g_host_plans.emplace(key, sp);
     return sp;
 }
@@ -252,7 +258,7 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form computes in FP64 (prec FP64 or FP32 output)");
     DevPlan *dp = nullptr;
-    int st = get_plan(N, M, P, Q, &dp);
+    int st = get_plan(N, M, P, Q, o.ring_cols, o.ring_rows, &dp);
     if (st != COVEST_OK) return st;
     const ShapePlan &sp = dp->sp;
     if (ws_bytes < sp.ws_bytes || (sp.ws_bytes > 0 && ws == nullptr))
@@ -426,6 +432,305 @@ AdjGeom adj_geometry(int N, int M, int P, int Q)
 
 }  // namespace
 
+// -------------------------------------------------------------- batches ----
+// A batched plan: one work list for every problem (longest job first), the
+// persistent main kernel, both finalize variants, all captured in one graph.
+struct covest_plan {
+    int device = 0;
+    covest_opts opts{};
+    int64_t count = 0;
+    hipStream_t own_stream = nullptr;
+    Job *d_jobs = nullptr;
+    LagGroup *d_groups = nullptr;
+    Inst *d_insts = nullptr;
+    FinItem *d_items[2] = {nullptr, nullptr};   // [0] table finalize, [1] per-lane finalize
+    unsigned int *d_counter = nullptr;
+    void *d_ws = nullptr;
+    int n_jobs = 0, n_items[2] = {0, 0}, grid = 0;
+    size_t lds_main = 0, lds_fin[2] = {0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double est_cost = 0.0;
+};
+
+namespace {
+
+void free_plan(covest_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    void *bufs[] = {p->d_jobs, p->d_groups, p->d_insts, p->d_items[0], p->d_items[1], p->d_counter, p->d_ws};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+    delete p;
+}
+
+// ------------------------------------------------------------- autotuner --
+// Ring widths (tile shapes of the main kernel) per (P, Q) class, chosen by
+// timing the main kernel on the largest problem of the class.  Results are
+// kept for the process and, when COVEST_TUNE_CACHE names a file, in that file
+// ("P Q W0 W1" per line).  COVEST_TUNE=0 keeps the default widths.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_path() { return std::getenv("COVEST_TUNE_CACHE"); }
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = tune_path();
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    int n = 0;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        int P, Q, w0, w1;
+        if (!(is >> P >> Q >> w0 >> w1) || P < 1 || Q < 1 ||
+            (w0 != 4 && w0 != 8 && w0 != 12 && w0 != 16) || (w1 != 4 && w1 != 8 && w1 != 12 && w1 != 16)) {
+            std::fprintf(stderr, "libcovest: ignoring malformed tune cache line in %s: '%s'\n", path, line.c_str());
+            continue;
+        }
+        g_tune[{P, Q}] = {w0, w1};
+        ++n;
+    }
+}
+
+void tune_store_locked(int P, int Q, int w0, int w1)
+{
+    g_tune[{P, Q}] = {w0, w1};
+    const char *path = tune_path();
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << P << " " << Q << " " << w0 << " " << w1 << "\n";
+}
+
+bool tuning_enabled()
+{
+    const char *s = std::getenv("COVEST_TUNE");
+    return !(s && s[0] == '0');
+}
+
+// Time rec_main for one problem and plan (events on a private stream).
+int time_main(const ShapePlan &sp, const covest_problem &p, const covest_opts &o, void *ws, void *R,
+              hipStream_t s, float *best_ms)
+{
+    Job *dj = nullptr;
+    LagGroup *dg = nullptr;
+    HIP_TRY(upload(&dj, sp.jobs));
+    HIP_TRY(upload(&dg, sp.groups));
+    MainArgs ma{};
+    ma.jobs = dj;
+    ma.groups = dg;
+    ma.n_jobs = (int)sp.jobs.size();
+    ma.xcd_remap = 1;
+    ma.use_inline = 1;
+    ma.inst_inline = make_inst(sp, p.A, p.M, R, (int64_t)p.P * p.Q, ws, o);
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float best = 1e30f;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 4 && e == hipSuccess && ma.n_jobs > 0; ++rep) {
+        (void)hipEventRecord(a, s);
+        e = launch_rec_main(ma, ma.n_jobs, sp.lds_main, s);
+        (void)hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(dj);
+    (void)hipFree(dg);
+    if (e != hipSuccess) return fail(COVEST_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
+    *best_ms = best;
+    return COVEST_OK;
+}
+
+// Widths for every (P, Q) class of the batch.
+int autotune(const covest_problem *pr, int64_t count, const covest_opts &o, int resident,
+             std::map<std::pair<int, int>, std::pair<int, int>> *out)
+{
+    std::map<std::pair<int, int>, int64_t> rep;   // class -> representative problem
+    for (int64_t i = 0; i < count; ++i) {
+        const auto key = std::make_pair((int)pr[i].P, (int)pr[i].Q);
+        auto it = rep.find(key);
+        if (it == rep.end() || (int64_t)pr[i].N * pr[i].M > (int64_t)pr[it->second].N * pr[it->second].M)
+            rep[key] = i;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    hipStream_t s = nullptr;
+    for (auto &kv : rep) {
+        const int P = kv.first.first, Q = kv.first.second;
+        auto hit = g_tune.find(kv.first);
+        if (hit != g_tune.end()) {
+            (*out)[kv.first] = hit->second;
+            continue;
+        }
+        if (!tuning_enabled()) continue;
+        if (!s) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        const covest_problem &p = pr[kv.second];
+        const std::vector<int> c0 = ring_width_candidates(Q), c1 = ring_width_candidates(P);
+        size_t ws_max = 0;
+        for (int w0 : c0)
+            for (int w1 : c1) ws_max = std::max(ws_max, make_shape_plan(p.N, p.M, P, Q, resident, w0, w1).ws_bytes);
+        void *ws = nullptr, *R = nullptr;
+        HIP_TRY(hipMalloc(&ws, std::max<size_t>(ws_max, 256)));
+        HIP_TRY(hipMalloc(&R, (size_t)P * Q * P * Q * 16));
+        // coordinate search: the column width first, then the row width
+        int b0 = c0[0], b1 = c1[0];
+        float best = 1e30f;
+        for (int w0 : c0) {
+            float ms;
+            int st = time_main(make_shape_plan(p.N, p.M, P, Q, resident, w0, b1), p, o, ws, R, s, &ms);
+            if (st != COVEST_OK) { (void)hipFree(ws); (void)hipFree(R); (void)hipStreamDestroy(s); return st; }
+            if (ms < best) { best = ms; b0 = w0; }
+        }
+        for (size_t k = 1; k < c1.size(); ++k) {
+            float ms;
+            int st = time_main(make_shape_plan(p.N, p.M, P, Q, resident, b0, c1[k]), p, o, ws, R, s, &ms);
+            if (st != COVEST_OK) { (void)hipFree(ws); (void)hipFree(R); (void)hipStreamDestroy(s); return st; }
+            if (ms < best) { best = ms; b1 = c1[k]; }
+        }
+        (void)hipFree(ws);
+        (void)hipFree(R);
+        tune_store_locked(P, Q, b0, b1);
+        (*out)[kv.first] = {b0, b1};
+    }
+    if (s) (void)hipStreamDestroy(s);
+    return COVEST_OK;
+}
+
+int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, const covest_opts &o,
+                  hipStream_t stream)
+{
+    HIP_TRY(hipGetDevice(&plan->device));
+    const int cus = cu_count(plan->device);
+    const int resident = 2 * cus;
+    HIP_TRY(prepare_rec_kernels());
+    std::map<std::pair<int, int>, std::pair<int, int>> widths;
+    if (!o.ring_cols && !o.ring_rows) {
+        int st = autotune(pr, count, o, resident, &widths);
+        if (st != COVEST_OK) return st;
+    }
+    auto wfor = [&](int P, int Q) {
+        if (o.ring_cols || o.ring_rows) return std::make_pair(o.ring_cols, o.ring_rows);
+        auto it = widths.find({P, Q});
+        return it == widths.end() ? std::make_pair(0, 0) : it->second;
+    };
+    // first pass: cost of every problem with a coarse plan
+    std::vector<double> cost(count, 0.0);
+    double total = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const auto w = wfor(pr[i].P, pr[i].Q);
+        const ShapePlan sp = make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, 1, w.first, w.second);
+        for (double c : sp.job_cost) cost[i] += c;
+        total += cost[i];
+    }
+    // second pass: split each problem into jobs of about a third of a resident slot's share
+    const double target = std::max(1.0, total / (3.0 * resident));
+    std::vector<Job> jobs;
+    std::vector<double> jcost;
+    std::vector<LagGroup> groups;
+    std::vector<Inst> insts(count);
+    std::vector<FinItem> items[2];
+    size_t ws_off = 0;
+    std::vector<size_t> ws_base(count);
+    std::vector<ShapePlan> plans(count);
+    for (int64_t i = 0; i < count; ++i) {
+        const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(resident, std::llround(cost[i] / target)));
+        const auto w = wfor(pr[i].P, pr[i].Q);
+        plans[i] = make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, slots, w.first, w.second);
+        ws_base[i] = ws_off;
+        ws_off += (plans[i].ws_bytes + 255) / 256 * 256;
+    }
+    HIP_TRY(hipMalloc(&plan->d_ws, std::max<size_t>(ws_off, 256)));
+    for (int64_t i = 0; i < count; ++i) {
+        const ShapePlan &sp = plans[i];
+        const int goff = (int)groups.size();
+        groups.insert(groups.end(), sp.groups.begin(), sp.groups.end());
+        for (size_t j = 0; j < sp.jobs.size(); ++j) {
+            Job jb = sp.jobs[j];
+            jb.inst = (int)i;
+            jb.group += goff;
+            jobs.push_back(jb);
+            jcost.push_back(sp.job_cost[j]);
+        }
+        const int var = sp.fin_table ? 0 : 1;
+        for (FinItem it : sp.items) {
+            it.inst = (int)i;
+            items[var].push_back(it);
+        }
+        plan->lds_main = std::max(plan->lds_main, sp.lds_main);
+        plan->lds_fin[var] = std::max(plan->lds_fin[var], sp.lds_fin);
+        insts[i] = make_inst(sp, pr[i].A, pr[i].M, pr[i].R, (int64_t)pr[i].P * pr[i].Q,
+                             static_cast<char *>(plan->d_ws) + ws_base[i], o);
+    }
+    // longest job first (stable, so equal jobs keep their spatial order)
+    std::vector<size_t> order(jobs.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return jcost[a] > jcost[b]; });
+    std::vector<Job> sorted;
+    sorted.reserve(jobs.size());
+    for (size_t j : order) sorted.push_back(jobs[j]);
+    plan->est_cost = total;
+    plan->n_jobs = (int)sorted.size();
+    plan->n_items[0] = (int)items[0].size();
+    plan->n_items[1] = (int)items[1].size();
+    plan->grid = std::max(1, std::min(resident, plan->n_jobs));
+    HIP_TRY(upload(&plan->d_jobs, sorted));
+    HIP_TRY(upload(&plan->d_groups, groups));
+    HIP_TRY(upload(&plan->d_insts, insts));
+    HIP_TRY(upload(&plan->d_items[0], items[0]));
+    HIP_TRY(upload(&plan->d_items[1], items[1]));
+    HIP_TRY(hipMalloc(&plan->d_counter, 256));
+
+    // capture: counter reset + persistent main kernel + finalize kernels
+    hipStream_t cs = stream;
+    if (cs == nullptr) {
+        HIP_TRY(hipStreamCreateWithFlags(&plan->own_stream, hipStreamNonBlocking));
+        cs = plan->own_stream;
+    }
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    if (plan->n_jobs > 0) {
+        MainArgs ma{};
+        ma.jobs = plan->d_jobs;
+        ma.groups = plan->d_groups;
+        ma.insts = plan->d_insts;
+        ma.n_jobs = plan->n_jobs;
+        ma.use_inline = 0;
+        e = launch_rec_persistent(ma, plan->d_counter, plan->grid, plan->lds_main, cs);
+    }
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+        if (plan->n_items[v] == 0) continue;
+        FinArgs fa{};
+        fa.items = plan->d_items[v];
+        fa.insts = plan->d_insts;
+        fa.n_items = plan->n_items[v];
+        fa.use_inline = 0;
+        e = launch_rec_finalize(fa, plan->n_items[v], plan->lds_fin[v], v == 0, cs);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(COVEST_ERR_HIP, "batched launch capture failed: %s", hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(COVEST_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    plan->graph = g;
+    HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    return COVEST_OK;
+}
+
+}  // namespace
+
 // =================================================================== ABI ====
 extern "C" {
 
@@ -459,7 +764,7 @@ int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q, const cove
     if (use_recurrence(o)) {
         if (P > kMaxWindow || Q > kMaxWindow)
             return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
-        *bytes = host_plan((int)N, (int)M, (int)P, (int)Q)->ws_bytes;
+        *bytes = host_plan((int)N, (int)M, (int)P, (int)Q, o.ring_cols, o.ring_rows)->ws_bytes;
         return ok();
     }
     const int prec = hankel_prec(o.prec);
@@ -554,31 +859,65 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
 int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,
                                const covest_opts *opts, hipStream_t stream)
 {
-    (void)out; (void)problems; (void)count; (void)opts; (void)stream;
-    return fail(COVEST_ERR_UNSUPPORTED, "batched plans are not available in this build");
+    if (!out || !problems || count < 1) return fail(COVEST_ERR_INVALID_ARG, "need out, problems and count >= 1");
+    *out = nullptr;
+    covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    if (o.form == COVEST_FORM_HANKEL_MFMA)
+        return fail(COVEST_ERR_UNSUPPORTED, "batched plans use the recurrence form");
+    if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
+        return fail(COVEST_ERR_UNSUPPORTED, "batched plans compute in FP64 (prec FP64 or FP32 output)");
+    for (int64_t i = 0; i < count; ++i) {
+        const covest_problem &p = problems[i];
+        st = check_shape(p.N, p.M, p.P, p.Q);
+        if (st != COVEST_OK) return fail(st, "problem %lld: %s", (long long)i, g_err.c_str());
+        if (!p.A || !p.R) return fail(COVEST_ERR_INVALID_ARG, "problem %lld: null A or R", (long long)i);
+        if (p.P > kMaxWindow || p.Q > kMaxWindow)
+            return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: P, Q <= %d", (long long)i, kMaxWindow);
+    }
+    covest_plan *plan = new covest_plan();
+    plan->opts = o;
+    plan->count = count;
+    st = build_batched(plan, problems, count, o, stream);
+    if (st != COVEST_OK) {
+        const std::string msg = g_err;
+        free_plan(plan);
+        return fail(st, "%s", msg.c_str());
+    }
+    *out = plan;
+    return ok();
 }
 
 int covest_forward_batched(covest_plan *plan, hipStream_t stream)
 {
-    (void)plan; (void)stream;
-    return fail(COVEST_ERR_UNSUPPORTED, "batched plans are not available in this build");
+    if (!plan || !plan->exec) return fail(COVEST_ERR_INVALID_ARG, "invalid plan");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device)
+        return fail(COVEST_ERR_PLAN_MISMATCH, "plan was built on device %d, current device is %d", plan->device, dev);
+    HIP_TRY(timed("batched_graph", stream, [&] { return hipGraphLaunch(plan->exec, stream); }));
+    return finish_call(stream);
 }
 
 int covest_plan_destroy(covest_plan *plan)
 {
-    (void)plan;
+    free_plan(plan);
     return ok();
 }
 
-int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots,
-                         covest_plan_info *out)
+static bool width_ok(int32_t w) { return w == 0 || w == 4 || w == 8 || w == 12 || w == 16; }
+
+int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t w0,
+                         int32_t w1, covest_plan_info *out)
 {
     if (!out) return fail(COVEST_ERR_INVALID_ARG, "out is null");
+    if (!width_ok(w0) || !width_ok(w1)) return fail(COVEST_ERR_INVALID_ARG, "ring widths are 0, 4, 8, 12 or 16");
     int st = check_shape(N, M, P, Q);
     if (st != COVEST_OK) return st;
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
-    const ShapePlan sp = make_shape_plan((int)N, (int)M, (int)P, (int)Q, n_slots > 0 ? n_slots : 512);
+    const ShapePlan sp = make_shape_plan((int)N, (int)M, (int)P, (int)Q, n_slots > 0 ? n_slots : 512, w0, w1);
     std::memset(out, 0, sizeof(*out));
     out->W0 = sp.W0;
     out->W1 = sp.W1;
@@ -602,14 +941,15 @@ int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_s
     return ok();
 }
 
-int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t *jobs,
-                       int32_t *groups, int32_t *items)
+int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t w0, int32_t w1,
+                       int32_t *jobs, int32_t *groups, int32_t *items)
 {
+    if (!width_ok(w0) || !width_ok(w1)) return fail(COVEST_ERR_INVALID_ARG, "ring widths are 0, 4, 8, 12 or 16");
     int st = check_shape(N, M, P, Q);
     if (st != COVEST_OK) return st;
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
-    const ShapePlan sp = make_shape_plan((int)N, (int)M, (int)P, (int)Q, n_slots > 0 ? n_slots : 512);
+    const ShapePlan sp = make_shape_plan((int)N, (int)M, (int)P, (int)Q, n_slots > 0 ? n_slots : 512, w0, w1);
     if (jobs) {
         for (size_t k = 0; k < sp.jobs.size(); ++k) {
             const Job &j = sp.jobs[k];

@@ -7,7 +7,11 @@
 
 namespace covest {
 
+// Sets the dynamic-LDS limits of every recurrence kernel (call before graph capture).
+hipError_t prepare_rec_kernels();
 hipError_t launch_rec_main(const MainArgs &ma, int n_blocks, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_rec_persistent(const MainArgs &ma, unsigned int *counter, int n_blocks, size_t lds_bytes,
+                                 hipStream_t stream);
 hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
                                hipStream_t stream);
 

@@ -67,15 +67,24 @@ static void add_groups(std::vector<LagGroup> &gs, int orient, int W, int d1lo, i
 
 static size_t tile_bytes(int rows, int cols) { return (size_t)rows * (size_t)(cols | 1) * 16; }
 
-ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots)
+std::vector<int> ring_width_candidates(int n)
+{
+    const int d = ring_width(n);
+    std::vector<int> c{d};
+    for (int w : {8, 12, 4})
+        if (w < d && (w >= 8 || n <= 8)) c.push_back(w);
+    return c;
+}
+
+ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0, int w1)
 {
     ShapePlan sp;
     sp.N = N;
     sp.M = M;
     sp.P = P;
     sp.Q = Q;
-    sp.W0 = ring_width(Q);
-    sp.W1 = ring_width(P);
+    sp.W0 = w0 > 0 ? w0 : ring_width(Q);
+    sp.W1 = w1 > 0 ? w1 : ring_width(P);
     sp.lag_stride = (2 * P - 1) * Q;
     sp.bandw = kWaves * sp.W0;
 

@@ -41,7 +41,11 @@ struct ShapePlan {
 };
 
 // n_slots: workgroups resident at once on the target device (2 per CU).
-ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots);
+// w0 / w1 override the ring widths along columns / rows (0: the default choice).
+ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0 = 0, int w1 = 0);
+
+// Ring widths worth trying for a window extent n (the first is the default).
+std::vector<int> ring_width_candidates(int n);
 
 // Plan of the plain (matrix-core) form for one shape and precision.
 struct HankelPlan {

@@ -228,11 +228,8 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return x * (n >> 3) + min(x, n & 7) + (b >> 3);
 }
 
-__global__ void __launch_bounds__(kThreads, 2) rec_main(MainArgs ma)
+__device__ __forceinline__ void run_job(const MainArgs &ma, int b, double2 *lds)
 {
-    extern __shared__ double2 lds[];
-    int b = blockIdx.x;
-    if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
     const Job job = ma.jobs[b];
     const Inst in = ma.use_inline ? ma.inst_inline : ma.insts[job.inst];
     const LagGroup g = ma.groups[job.group];
@@ -252,6 +249,36 @@ __global__ void __launch_bounds__(kThreads, 2) rec_main(MainArgs ma)
         }
     }
 }
+
+// One workgroup per job (single problems).
+__global__ void __launch_bounds__(kThreads, 2) rec_main(MainArgs ma)
+{
+    extern __shared__ double2 lds[];
+    int b = blockIdx.x;
+    if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
+    run_job(ma, b, lds);
+}
+
+// Persistent form for batches: every resident workgroup claims the next job
+// of the (longest-first) work list from a device counter until the list is
+// exhausted (Sec. 3.4: a free core simply takes the next combination).  Each
+// job writes its own outputs, so results do not depend on which workgroup ran
+// which job.
+__global__ void __launch_bounds__(kThreads, 2) rec_main_persistent(MainArgs ma, unsigned int *counter)
+{
+    extern __shared__ double2 lds[];
+    __shared__ int s_job;
+    for (;;) {
+        if (threadIdx.x == 0) s_job = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int j = s_job;
+        __syncthreads();
+        if (j >= ma.n_jobs) break;
+        run_job(ma, j, lds);
+    }
+}
+
+__global__ void reset_counter(unsigned int *counter) { *counter = 0u; }
 
 // ---------------------------------------------------------------------------
 // Finalize: one wave per unique combination.
@@ -505,32 +532,47 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 // Host launch helpers
 // ---------------------------------------------------------------------------
 
+hipError_t prepare_rec_kernels()
+{
+    static hipError_t status = [] {
+        const void *fns[] = {reinterpret_cast<const void *>(&rec_main),
+                             reinterpret_cast<const void *>(&rec_main_persistent),
+                             reinterpret_cast<const void *>(&rec_finalize),
+                             reinterpret_cast<const void *>(&rec_finalize_tab)};
+        for (const void *f : fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }();
+    return status;
+}
+
 hipError_t launch_rec_main(const MainArgs &ma, int n_blocks, size_t lds_bytes, hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_main),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    hipError_t e = prepare_rec_kernels();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rec_main, dim3(n_blocks), dim3(kThreads), lds_bytes, stream, ma);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_persistent(const MainArgs &ma, unsigned int *counter, int n_blocks, size_t lds_bytes,
+                                 hipStream_t stream)
+{
+    hipError_t e = prepare_rec_kernels();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rec_main_persistent, dim3(n_blocks), dim3(kThreads), lds_bytes, stream, ma, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
                                hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_finalize),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_finalize_tab),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    hipError_t e = prepare_rec_kernels();
+    if (e != hipSuccess) return e;
     if (table)
         hipLaunchKernelGGL(rec_finalize_tab, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else

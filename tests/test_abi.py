@@ -55,6 +55,8 @@ def test_workspace_query_errors():
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     assert L.covest_workspace_size(300, 300, 80, 8, _opts(form="recurrence"), ctypes.byref(n)) \
         == cv.ERR_UNSUPPORTED
+    bad = cv.make_opts(ring_cols=6)
+    assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     assert L.covest_workspace_size(64, 64, 8, 8, None, ctypes.byref(n)) == cv.OK
     assert n.value == cv.plan_info(64, 64, 8, 8)["ws_bytes"]
 

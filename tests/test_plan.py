@@ -151,11 +151,15 @@ SHAPES = [(64, 64, 8, 8), (256, 256, 16, 16), (1024, 1024, 32, 32), (512, 512, 1
           (130, 200, 3, 1), (50, 50, 1, 1), (200, 200, 40, 24)]
 
 
+WIDTHS = [(0, 0), (8, 8), (4, 16), (16, 4), (12, 12)]
+
+
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("n_slots", [512, 64])
-def test_plan_ownership(shape, n_slots):
+@pytest.mark.parametrize("n_slots", [512, 64, 1])
+@pytest.mark.parametrize("widths", WIDTHS, ids=lambda w: f"w{w[0]}_{w[1]}")
+def test_plan_ownership(shape, n_slots, widths):
     N, M, P, Q = shape
-    info, jobs, groups, items = cv.plan_tables(N, M, P, Q, n_slots)
+    info, jobs, groups, items = cv.plan_tables(N, M, P, Q, n_slots, *widths)
     Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
     assert P - 1 <= Rm0 <= Rm1 <= max(Rm0, N - P + 1)
     assert Q - 1 <= Cm0 <= Cm1 <= max(Cm0, M - Q + 1)
@@ -205,6 +209,12 @@ def test_plan_ownership(shape, n_slots):
     # products: the main kernel keeps all but the corner products
     c = cv.counts(N, M, P, Q)
     assert info["main_products"] + info["fin_products"] == c["um"]
+
+
+def test_width_errors():
+    with pytest.raises(cv.CovestError) as e:
+        cv.plan_info(64, 64, 8, 8, 512, 5, 0)
+    assert e.value.status == cv.ERR_INVALID_ARG
 
 
 def test_plan_cfg3_fills_the_gpu():
@@ -268,6 +278,11 @@ def model_forward(A, P, Q, info):
 def test_decomposition_reproduces_oracle(oracle_mod, shape):
     N, M, P, Q = shape
     A = synth.small_int(N, M, seed=N + 7 * M)
+    for widths in WIDTHS:
+        info = cv.plan_info(N, M, P, Q, 512, *widths)
+        R = model_forward(A, P, Q, info)
+        ref = oracle_mod.forward(A, P, Q)
+        assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag), widths
     info = cv.plan_info(N, M, P, Q)
     R = model_forward(A, P, Q, info)
     ref = oracle_mod.forward(A, P, Q)
