@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
     ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     return ap.parse_args()
 
 
@@ -76,6 +77,57 @@ def cpu_baseline(A, eta, seconds):
             "sample": f"{n_big} random upper-triangle entries of R for the same 1024x1024 input "
                       f"and 32x32 window (of {eta}), each a direct FP64 sum over all 986049 "
                       f"positions, {dt:.1f} s on {threads} threads; scaled by {eta}/{n_big}"}
+
+
+import numpy as np  # noqa: E402
+
+
+def extra_workloads(covest, synth, torch, dev):
+    """The batch workload (512 uneven problems in one graph replay) and the
+    differentiation workload (512 x 512, 16 x 16: forward + adjoint)."""
+    out = {}
+    batch = synth.batch(512, seed=4)
+    As = [torch.from_numpy(A).to(dev) for (A, P, Q) in batch]
+    t0 = time.perf_counter()
+    plan = covest.BatchedPlan([(At, P, Q) for At, (A, P, Q) in zip(As, batch)])
+    t_plan = time.perf_counter() - t0
+    for _ in range(2):
+        plan.run()
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    um = sum(covest.counts(A.shape[0], A.shape[1], P, Q)["um"] for (A, P, Q) in batch)
+    out["batched"] = {"workload": "512 Gaussian inputs, N, M uniform in [64, 512], P, Q in {4, 8, 12, 16} "
+                                  "(seed 4), FP64, one graph replay",
+                      "ms_per_batch": dt * 1e3, "matrices_per_s": 512 / dt,
+                      "gflops_algorithmic": 8.0 * um / dt / 1e9, "plan_s": t_plan}
+    print(f"[bench] batched: {dt * 1e3:.3f} ms per 512 matrices", file=sys.stderr, flush=True)
+    plan.close()
+    del As
+    A, W, At = synth.adjoint_inputs()
+    Ad = torch.from_numpy(A).to(dev)
+    G = torch.from_numpy(W.astype(np.complex64)).to(dev)
+    Rf = covest.covest_forward(Ad, 16, 16)
+    dA = covest.covest_backward(Ad, G, 16, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        covest.covest_forward(Ad, 16, 16, out=Rf)
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    for _ in range(20):
+        dA = covest.covest_backward(Ad, G, 16, 16)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / 20
+    out["adjoint"] = {"workload": "A 512x512, 16x16 window: forward (FP64) and adjoint",
+                      "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+                      "backward_complex_macs": 512 * 512 * 31 * 31}
+    return out
 
 
 def main():
@@ -182,6 +234,10 @@ def main():
                   file=sys.stderr, flush=True)
             del wsp, Rp
 
+    extra = {}
+    if not args.no_extra:
+        extra = extra_workloads(covest, synth, torch, dev)
+
     f_nom = 8.0 * cnt["K"] * cnt["eta"]         # plain-form flops: every product recomputed
     f_alg = 8.0 * cnt["um"]                     # each distinct product once
     out = {
@@ -209,6 +265,7 @@ def main():
                        if "fp32" in plain else None),
         "speedup_vs_plain_fp32": (value / plain["fp32"]["matrices_per_s"]) if "fp32" in plain else None,
         "other_forms": {k: v for k, v in plain.items() if k != "fp32"},
+        **extra,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None},
