@@ -13,6 +13,10 @@ algorithmic flops per launch are 8 flops per distinct product it keeps (one
 complex multiply-accumulate, x * conj(y) into an FP64 sum), times the number of
 such products; its duration comes from HIP events recorded around each launch
 on the stream the kernel runs on.  The peak is the FP64 vector rate of MI355X.
+Its "traffic" is the HBM bytes one launch reads and writes, from rocprofv3's
+FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain copy of
+known size (``--copy-calibration``); it is null unless the recorded summary was
+taken on the current kernel sources.
 """
 from __future__ import annotations
 
@@ -45,7 +49,60 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
     ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device copies of 256 MiB (the reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     return ap.parse_args()
+
+
+# HBM traffic of rec_main comes from hardware counters taken with rocprofv3 on this
+# workload; the summary records the sources it was measured on, and is used only
+# while they are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rec_main_1024x1024_w32x32_traffic.txt")
+TRAFFIC_SOURCES = ["paper_1303_2285_amd/csrc/rec_kernels.hip",
+                   "paper_1303_2285_amd/csrc/covest_internal.hpp",
+                   "paper_1303_2285_amd/csrc/plan.cpp",
+                   "paper_1303_2285_amd/csrc/plan.hpp"]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per rec_main launch (read + written), or None if not measured for these sources."""
+    try:
+        fields = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                k, sep, v = line.partition(":")
+                if sep:
+                    fields[k.strip()] = v.strip()
+        if fields.get("sources_sha256_16") != sources_digest():
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+    n = 64 * 1024 * 1024                      # 256 MiB of float32
+    x = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 4 * n,
+                                           "bytes_written_per_copy": 4 * n, "copies": 5}}),
+          flush=True)
 
 
 def cpu_baseline(A, eta, seconds):
@@ -137,6 +194,9 @@ def main():
               "(the path is single-GPU; see the design notes for how it would shard)",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -268,7 +328,7 @@ def main():
         **extra,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic()},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A_np, cnt["eta"], args.cpu_seconds)
