@@ -5,14 +5,17 @@
 Workload: A is 1024 x 1024 complex64 (N(0,1) noise plus one 2-D complex
 exponential of amplitude 1e3, seed 3), window 32 x 32, so R is 1024 x 1024 over
 993^2 = 986049 window positions.  A step is one full forward call of the chosen
-form (the diagonal-segment recurrence with FP64 sums, complex128 R) with A
+form (the diagonal-segment recurrence with FP64 sums, complex128 R, main pass
+on the engine the library picks: the FP64 matrix cores for this window) with A
 already resident in device memory.  Prints one JSON line.
 
-The "roofline" object describes the dominant kernel (rec_main): its
-algorithmic flops per launch are 8 flops per distinct product it keeps (one
-complex multiply-accumulate, x * conj(y) into an FP64 sum), times the number of
-such products; its duration comes from HIP events recorded around each launch
-on the stream the kernel runs on.  The peak is the FP64 vector rate of MI355X.
+The "roofline" object describes the dominant kernel (the main pass, rec_mfma
+or rec_main): its algorithmic flops per launch are 8 flops per distinct
+product it keeps (one complex multiply-accumulate, x * conj(y) into an FP64
+sum), times the number of such products; its duration comes from HIP events
+recorded around each launch on the stream the kernel runs on.  The peak is
+MI355X's FP64 rate, the same 78.6 TFLOP/s for the vector units and the
+matrix cores.
 Its "traffic" is the HBM bytes one launch reads and writes, from rocprofv3's
 FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain copy of
 known size (``--copy-calibration``); it is null unless the recorded summary was
@@ -32,7 +35,7 @@ if ROOT not in sys.path:
 
 METRIC = ("R matrices/s + GFLOP/s, 1024² A, 32×32 window: chosen vs plain form "
           "at rel err ≤1e-5")
-FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 64 FP64 FMA lanes x 2 flops
+FP64_PEAK_TFLOPS = 78.6     # FP64 vector and FP64 matrix (dense) alike: 256 CUs x 2.4 GHz x 64 FMA x 2
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense, per the datasheet
 PLAIN_FORMS = [("fp32", 1, "fp32"), ("bf16x3", 3, "bf16"), ("fp16x3", 3, "fp16"),
                ("fp16", 1, "fp16"), ("bf16", 1, "bf16")]   # (precision, passes, peak key)
@@ -55,35 +58,41 @@ def parse():
     return ap.parse_args()
 
 
-# HBM traffic of rec_main comes from hardware counters taken with rocprofv3 on this
-# workload; the summary records the sources it was measured on, and is used only
-# while they are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rec_main_1024x1024_w32x32_traffic.txt")
-TRAFFIC_SOURCES = ["paper_1303_2285_amd/csrc/rec_kernels.hip",
-                   "paper_1303_2285_amd/csrc/covest_internal.hpp",
-                   "paper_1303_2285_amd/csrc/plan.cpp",
-                   "paper_1303_2285_amd/csrc/plan.hpp"]
+# HBM traffic of the main kernel comes from hardware counters taken with
+# rocprofv3 on this workload; the summary records the sources it was measured
+# on, and is used only while they are unchanged.
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_1024x1024_w32x32_traffic.txt")
 
 
-def sources_digest():
+TRAFFIC_SOURCES = {
+    "rec_main": ["paper_1303_2285_amd/csrc/rec_kernels.hip", "paper_1303_2285_amd/csrc/covest_internal.hpp",
+                 "paper_1303_2285_amd/csrc/plan.cpp", "paper_1303_2285_amd/csrc/plan.hpp"],
+    "rec_mfma": ["paper_1303_2285_amd/csrc/rec_mfma.hip", "paper_1303_2285_amd/csrc/covest_internal.hpp",
+                 "paper_1303_2285_amd/csrc/device_util.hpp", "paper_1303_2285_amd/csrc/plan.cpp",
+                 "paper_1303_2285_amd/csrc/plan.hpp"],
+}
+
+
+def sources_digest(kernel):
     import hashlib
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in TRAFFIC_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """Bytes per rec_main launch (read + written), or None if not measured for these sources."""
+def measured_traffic(kernel):
+    """Bytes per launch of `kernel` (read + written), or None if not measured for these sources."""
     try:
         fields = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(kernel)) as f:
             for line in f:
                 k, sep, v = line.partition(":")
                 if sep:
                     fields[k.strip()] = v.strip()
-        if fields.get("sources_sha256_16") != sources_digest():
+        if fields.get("sources_sha256_16") != sources_digest(kernel):
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -234,12 +243,44 @@ def main():
     torch.cuda.synchronize()
     rec = covest.timing_read()
     covest.timing_enable(False)
-    main_launches, main_ms = rec.get("rec_main", (0, 0.0))
+    main_name = "rec_mfma" if "rec_mfma" in rec else "rec_main"
+    engine = "matrix" if main_name == "rec_mfma" else "vector"
+    main_launches, main_ms = rec.get(main_name, (0, 0.0))
     fin_launches, fin_ms = rec.get("rec_finalize", (0, 0.0))
     main_avg_ms = main_ms / max(1, main_launches)
     fin_avg_ms = fin_ms / max(1, fin_launches)
-    flops_main = 8.0 * info["main_products"]
+    main_products = (covest.mfma_plan(N, M, P, Q)[0] if engine == "matrix" else info)["main_products"]
+    flops_main = 8.0 * main_products
     achieved_tf = flops_main / (main_avg_ms * 1e-3) / 1e12
+
+    # The other engine of the recurrence on the same input, for comparison.
+    vec = None
+    if engine == "matrix":
+        wsv = torch.empty(max(1, covest.workspace_size(N, M, P, Q, engine="vector")), dtype=torch.uint8,
+                          device=dev)
+        Rv = torch.empty_like(R)
+        runv = lambda: covest.covest_forward(A, P, Q, out=Rv, workspace=wsv, engine="vector")
+        for _ in range(args.warmup):
+            runv()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            runv()
+        torch.cuda.synchronize()
+        vms = 1e3 * (time.perf_counter() - t0) / args.steps
+        covest.timing_reset()
+        covest.timing_enable(True)
+        for _ in range(20):
+            runv()
+        torch.cuda.synchronize()
+        rv = covest.timing_read()
+        covest.timing_enable(False)
+        vmain = rv["rec_main"][1] / rv["rec_main"][0]
+        vec = {"ms_per_step": vms, "matrices_per_s": 1e3 / vms, "rec_main_ms": vmain,
+               "rec_main_tflops": 8.0 * info["main_products"] / (vmain * 1e-3) / 1e12,
+               "max_abs_diff_vs_matrix": float((Rv - R).abs().max().item())}
+        print(f"[bench] vector engine: {vms:.4f} ms/step", file=sys.stderr, flush=True)
+        del wsv, Rv
 
     # Accuracy of the timed result on sampled entries (the oracle's direct sums).
     R_h = R.cpu().numpy()
@@ -315,10 +356,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "A 1024x1024 complex64 (N(0,1) + 1e3 2-D exponential, seed 3), "
                                "32x32 window, R 1024x1024 complex128 over 993^2 positions",
-                   "form": "recurrence", "precision": "fp64", "N": N, "M": M, "P": P, "Q": Q},
+                   "form": "recurrence", "engine": engine, "precision": "fp64",
+                   "N": N, "M": M, "P": P, "Q": Q},
         "gflops_effective": f_nom / (ms_per_step * 1e-3) / 1e9,
         "gflops_algorithmic": f_alg / (ms_per_step * 1e-3) / 1e9,
-        "kernels_ms": {"rec_main": main_avg_ms, "rec_finalize": fin_avg_ms},
+        "kernels_ms": {main_name: main_avg_ms, "rec_finalize": fin_avg_ms},
+        "vector_engine": vec,
         "rel_err_sampled_max": sampled_err,
         "rel_err_sampled": chosen_rel,
         "plain_form": ({"form": "hankel_mfma", "precision": "fp32", **plain["fp32"]}
@@ -326,9 +369,10 @@ def main():
         "speedup_vs_plain_fp32": (value / plain["fp32"]["matrices_per_s"]) if "fp32" in plain else None,
         "other_forms": {k: v for k, v in plain.items() if k != "fp32"},
         **extra,
-        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic()},
+        "roofline": {"bound": "mfma" if engine == "matrix" else "alu", "kernel": main_name,
+                     "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(main_name)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A_np, cnt["eta"], args.cpu_seconds)

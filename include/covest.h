@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define COVEST_VERSION 1
+#define COVEST_VERSION 2
 
 typedef enum {
     COVEST_OK = 0,
@@ -73,13 +73,27 @@ typedef enum {
     COVEST_FILL_UPPER = 1   /* entries with k2 >= k1 only; the lower triangle is untouched */
 } covest_fill;
 
+/* Which units run the main pass of the recurrence.  Both compute the same
+ * FP64 sums of the same products (each distinct product once, Sec. 3.3); they
+ * differ in speed and in the order of the additions. */
+typedef enum {
+    COVEST_ENGINE_AUTO = 0,    /* matrix cores where the window suits them, else vector  */
+    COVEST_ENGINE_VECTOR = 1,  /* FP64 FMA on the vector units, lags in a register ring  */
+    COVEST_ENGINE_MATRIX = 2   /* FP64 MFMA: per line, a block of A times a Toeplitz band
+                                  of the line; needs N >= 2P-1, M >= 2Q-1 and a lag block
+                                  of at most 8 tiles of 16 x 16 with little padding
+                                  (COVEST_ERR_UNSUPPORTED otherwise)                     */
+} covest_engine;
+
 typedef struct {
     covest_form form;
     covest_precision prec;
     covest_fill fill;
     int normalize;          /* 1: R = C / K (default); 0: the paper's unnormalised C       */
-    int ring_cols;          /* recurrence tile shape: lags per lane along columns (dc) and  */
-    int ring_rows;          /* along rows (dr): 4, 8, 12 or 16; 0 = the library's choice    */
+    int ring_cols;          /* vector engine tile shape: lags per lane along columns (dc)   */
+    int ring_rows;          /* and along rows (dr): 4, 8, 12 or 16; 0 = the library's choice;
+                               a non-zero width makes AUTO pick the vector engine           */
+    int engine;             /* covest_engine (recurrence form only)                         */
 } covest_opts;
 
 /* Work counts of the method for one shape (Sec. 3.2-4.1):

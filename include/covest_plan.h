@@ -49,6 +49,31 @@ int covest_plan_info_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_s
 int covest_plan_tables(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_slots, int32_t w0, int32_t w1,
                        int32_t *jobs, int32_t *groups, int32_t *items);
 
+/* Plan of the matrix-core engine (COVEST_ENGINE_MATRIX) for n_cu compute
+ * units.  The middle block is exact: rows [P-1, N-P+1), columns [Q-1, M-Q+1).
+ * A first-factor line (a row of A for orientation 0, a column for 1) is
+ * walked in k-groups of 4 second-factor positions; each workgroup job covers
+ * a range of (block of 8 lines, k-group) pairs.  Bulk jobs (kind 0) add
+ * their sums into partial row `out`; strip jobs (kind 1) cover one block and
+ * one piece of its k-groups, and line l writes z row out + (l - line0), where
+ * z rows are numbered piece * (individual lines) + individual index. */
+typedef struct {
+    int32_t mt, nt;             /* 16 x 16 tiles of the lag block: rows dr, columns dc  */
+    int32_t Rm0, Rm1, Cm0, Cm1; /* middle rows / columns                               */
+    int32_t n_ir, n_ic;         /* individual rows / columns                           */
+    int32_t lag_stride;         /* (2P-1)Q                                             */
+    int32_t n_bulk, n_jobs, n_items;
+    int32_t zpieces;            /* pieces per strip line                               */
+    int64_t ws_bytes, lds_main, lds_fin, main_products, fin_products;
+} covest_mfma_plan_info;
+
+/* Fills *out and, when non-null, the job rows (16 int32 each: inst, orient,
+ * kind, out, line0, line_end, b0, kg0, b1, kg1, n_kg, pos_lo, pos_hi, k0, 0, 0)
+ * and the finalize item rows (5 int32 each, as covest_plan_tables).
+ * COVEST_ERR_UNSUPPORTED when the engine cannot run the shape. */
+int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
+                         covest_mfma_plan_info *out, int32_t *jobs, int32_t *items);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ ERR_PLAN_MISMATCH = -6
 FORMS = {"auto": 0, "recurrence": 1, "hankel": 2, "hankel_mfma": 2}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3, "bf16": 4, "fp16": 5}
 FILLS = {"full": 0, "upper": 1}
+ENGINES = {"auto": 0, "vector": 1, "matrix": 2}
 
 
 class CovestError(RuntimeError):
@@ -38,7 +39,8 @@ class CovestError(RuntimeError):
 
 class covest_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("prec", ctypes.c_int), ("fill", ctypes.c_int),
-                ("normalize", ctypes.c_int), ("ring_cols", ctypes.c_int), ("ring_rows", ctypes.c_int)]
+                ("normalize", ctypes.c_int), ("ring_cols", ctypes.c_int), ("ring_rows", ctypes.c_int),
+                ("engine", ctypes.c_int)]
 
 
 class covest_counts_t(ctypes.Structure):
@@ -62,6 +64,13 @@ class covest_plan_info(ctypes.Structure):
                                                "n_items")] + \
                [(n, ctypes.c_int64) for n in ("ws_bytes", "lds_main", "lds_fin", "main_products",
                                                "fin_products")]
+
+
+class covest_mfma_plan_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("mt", "nt", "Rm0", "Rm1", "Cm0", "Cm1", "n_ir", "n_ic",
+                                               "lag_stride", "n_bulk", "n_jobs", "n_items", "zpieces")] + \
+               [(n, ctypes.c_int64) for n in ("ws_bytes", "lds_main", "lds_fin", "main_products",
+                                              "fin_products")]
 
 
 # Every symbol the headers declare, with its ctypes signature.
@@ -94,6 +103,8 @@ SIGNATURES = {
                                     ctypes.c_int32, ctypes.POINTER(covest_plan_info)]),
     "covest_plan_tables": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "covest_mfma_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
+                                    ctypes.POINTER(covest_mfma_plan_info), ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -125,7 +136,7 @@ def _check(status: int):
 
 
 def make_opts(form="auto", precision="fp64", fill="full", normalize=True, ring_cols=0,
-              ring_rows=0) -> covest_opts:
+              ring_rows=0, engine="auto") -> covest_opts:
     o = covest_opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.prec = PRECS[precision] if isinstance(precision, str) else int(precision)
@@ -133,6 +144,7 @@ def make_opts(form="auto", precision="fp64", fill="full", normalize=True, ring_c
     o.normalize = 1 if normalize else 0
     o.ring_cols = int(ring_cols)
     o.ring_rows = int(ring_rows)
+    o.engine = ENGINES[engine] if isinstance(engine, str) else int(engine)
     return o
 
 
@@ -193,16 +205,17 @@ def _workspace(nbytes: int, device):
 
 
 def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="full",
-                   normalize=True, out=None, workspace=None, ring_cols=0, ring_rows=0):
+                   normalize=True, out=None, workspace=None, ring_cols=0, ring_rows=0, engine="auto"):
     """R = (1/K) sum_{p,q} V^{p,q} (V^{p,q})^H for the complex64 N x M tensor A.
 
     Returns a PQ x PQ tensor (complex128 for precision "fp64", complex64
-    otherwise) on A's device, computed on the current stream.
+    otherwise) on A's device, computed on the current stream.  `engine`
+    ("auto", "vector", "matrix") picks the units of the recurrence's main pass.
     """
     torch = _torch()
     _check_input(A)
     N, M = A.shape
-    o = make_opts(form, precision, fill, normalize, ring_cols, ring_rows)
+    o = make_opts(form, precision, fill, normalize, ring_cols, ring_rows, engine)
     PQ = P * Q
     rdtype = torch.complex128 if o.prec == 0 else torch.complex64
     if out is None:
@@ -214,7 +227,7 @@ def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="fu
         if R.dtype != rdtype or R.shape != (PQ, PQ) or R.stride(1) != 1:
             raise ValueError("out has the wrong dtype, shape or layout")
     need = workspace_size(N, M, P, Q, form=form, precision=precision, fill=fill,
-                          normalize=normalize, ring_cols=ring_cols, ring_rows=ring_rows)
+                          normalize=normalize, ring_cols=ring_cols, ring_rows=ring_rows, engine=engine)
     if workspace is None or workspace.numel() < need:
         ws, nbytes = _workspace(need, A.device)
     else:
@@ -378,3 +391,16 @@ def plan_tables(N, M, P, Q, n_slots=512, w0=0, w1=0):
 
 def version() -> int:
     return int(lib().covest_version())
+
+
+def mfma_plan(N, M, P, Q, n_cu=256):
+    """(info, jobs[n,16], items[n,5]) of the matrix-core engine's plan (host only)."""
+    import numpy as np
+    info = covest_mfma_plan_info()
+    _check(lib().covest_mfma_plan_get(N, M, P, Q, n_cu, ctypes.byref(info), None, None))
+    d = {name: getattr(info, name) for name, _ in covest_mfma_plan_info._fields_}
+    jobs = np.zeros((d["n_jobs"], 16), dtype=np.int32)
+    items = np.zeros((d["n_items"], 5), dtype=np.int32)
+    _check(lib().covest_mfma_plan_get(N, M, P, Q, n_cu, ctypes.byref(info), jobs.ctypes.data,
+                                      items.ctypes.data))
+    return d, jobs, items

@@ -105,6 +105,7 @@ covest_opts resolve_opts(const covest_opts *o)
     r.fill = COVEST_FILL_FULL;
     r.normalize = 1;
     r.ring_cols = r.ring_rows = 0;
+    r.engine = COVEST_ENGINE_AUTO;
     if (o) r = *o;
     return r;
 }
@@ -120,6 +121,8 @@ int check_opts(const covest_opts &o)
     for (int w : {o.ring_cols, o.ring_rows})
         if (w != 0 && w != 4 && w != 8 && w != 12 && w != 16)
             return fail(COVEST_ERR_INVALID_ARG, "ring widths are 0, 4, 8, 12 or 16 (got %d)", w);
+    if (o.engine < COVEST_ENGINE_AUTO || o.engine > COVEST_ENGINE_MATRIX)
+        return fail(COVEST_ERR_INVALID_ARG, "unknown engine %d", (int)o.engine);
     return COVEST_OK;
 }
 
@@ -144,18 +147,38 @@ struct DevPlan {
     Job *d_jobs = nullptr;
     LagGroup *d_groups = nullptr;
     FinItem *d_items = nullptr;
+    MJob *d_mjobs = nullptr;
     int xcd_remap = 0;
 };
 
+using PlanKey = std::tuple<int, int, int, int, int, int, int, int>;
 std::mutex g_pmu;
-std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<DevPlan>> g_plans;
+std::map<PlanKey, std::unique_ptr<DevPlan>> g_plans;
 
-int n_slots_for_device(int dev)
+int cus_of_device(int dev)
 {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    return 2 * cus;
+    return cus;
+}
+
+int n_slots_for_device(int dev) { return 2 * cus_of_device(dev); }
+
+// Engine of the recurrence's main pass for this shape and options: 1 vector,
+// 2 matrix cores, 0 when the requested engine cannot run the shape.
+int pick_engine(int N, int M, int P, int Q, const covest_opts &o)
+{
+    const bool fits = mfma_fits(N, M, P, Q);
+    if (o.engine == COVEST_ENGINE_MATRIX) return fits ? 2 : 0;
+    if (o.engine == COVEST_ENGINE_VECTOR) return 1;
+    return (fits && o.ring_cols == 0 && o.ring_rows == 0) ? 2 : 1;
+}
+
+ShapePlan plan_for(int N, int M, int P, int Q, int cus, int w0, int w1, int engine)
+{
+    if (engine == 2) return make_mfma_plan(N, M, P, Q, cus);
+    return make_shape_plan(N, M, P, Q, 2 * cus, w0, w1);
 }
 
 template <class T>
@@ -168,11 +191,11 @@ hipError_t upload(T **dst, const std::vector<T> &src)
     return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
-int get_plan(int N, int M, int P, int Q, int w0, int w1, DevPlan **out)
+int get_plan(int N, int M, int P, int Q, int w0, int w1, int engine, DevPlan **out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    auto key = std::make_tuple(dev, N, M, P, Q, w0, w1);
+    auto key = std::make_tuple(dev, N, M, P, Q, w0, w1, engine);
     std::lock_guard<std::mutex> lk(g_pmu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
@@ -180,29 +203,30 @@ int get_plan(int N, int M, int P, int Q, int w0, int w1, DevPlan **out)
         return COVEST_OK;
     }
     auto dp = std::make_unique<DevPlan>();
-    dp->sp = make_shape_plan(N, M, P, Q, n_slots_for_device(dev), w0, w1);
+    dp->sp = plan_for(N, M, P, Q, cus_of_device(dev), w0, w1, engine);
     HIP_TRY(upload(&dp->d_jobs, dp->sp.jobs));
     HIP_TRY(upload(&dp->d_groups, dp->sp.groups));
     HIP_TRY(upload(&dp->d_items, dp->sp.items));
-    dp->xcd_remap = dp->sp.jobs.empty() ? 0 : 1;
+    HIP_TRY(upload(&dp->d_mjobs, dp->sp.mjobs));
+    dp->xcd_remap = 1;
     *out = dp.get();
     g_plans.emplace(key, std::move(dp));
     return COVEST_OK;
 }
 
 std::mutex g_hmu;
-std::map<std::tuple<int, int, int, int, int, int, int>, std::shared_ptr<const ShapePlan>> g_host_plans;
+std::map<PlanKey, std::shared_ptr<const ShapePlan>> g_host_plans;
 
 // Host-only planning, cached (workspace queries must work without a device).
-std::shared_ptr<const ShapePlan> host_plan(int N, int M, int P, int Q, int w0, int w1)
+std::shared_ptr<const ShapePlan> host_plan(int N, int M, int P, int Q, int w0, int w1, int engine)
 {
-    int dev = 0, slots = 512;
-    if (hipGetDevice(&dev) == hipSuccess) slots = n_slots_for_device(dev);
-    auto key = std::make_tuple(slots, N, M, P, Q, w0, w1);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) cus = cus_of_device(dev);
+    auto key = std::make_tuple(cus, N, M, P, Q, w0, w1, engine);
     std::lock_guard<std::mutex> lk(g_hmu);
     auto it = g_host_plans.find(key);
     if (it != g_host_plans.end()) return it->second;
-    auto sp = std::make_shared<const ShapePlan>(make_shape_plan(N, M, P, Q, slots, w0, w1));
+    auto sp = std::make_shared<const ShapePlan>(plan_for(N, M, P, Q, cus, w0, w1, engine));
     g_host_plans.emplace(key, sp);
     return sp;
 }
@@ -233,10 +257,11 @@ Inst make_inst(const ShapePlan &sp, const void *A, int64_t lda, void *R, int64_t
     double *base = static_cast<double *>(ws);
     in.partial = base;
     in.zr = base + (size_t)2 * sp.lag_stride * sp.n_bulk;
-    in.zc = in.zr + (size_t)2 * sp.lag_stride * sp.n_ir;
+    in.zc = in.zr + (size_t)2 * sp.lag_stride * sp.n_ir * sp.zpieces;
     in.out_fp64 = o.prec == COVEST_PREC_FP64 ? 1 : 0;
     in.fill_full = o.fill == COVEST_FILL_FULL ? 1 : 0;
     in.normalize = o.normalize ? 1 : 0;
+    in.zpieces = sp.zpieces;
     return in;
 }
 
@@ -257,14 +282,35 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
     if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form computes in FP64 (prec FP64 or FP32 output)");
+    int engine = pick_engine(N, M, P, Q, o);
+    if (engine == 0)
+        return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N >= 2P-1, M >= 2Q-1 and a lag "
+                                            "block of at most 8 tiles of 16 x 16 with little padding");
+    // the matrix-core kernel addresses A with 32-bit element offsets
+    if (engine == 2 && (int64_t)N * lda + M >= ((int64_t)1 << 31)) {
+        if (o.engine == COVEST_ENGINE_MATRIX)
+            return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N * lda < 2^31");
+        engine = 1;
+    }
     DevPlan *dp = nullptr;
-    int st = get_plan(N, M, P, Q, o.ring_cols, o.ring_rows, &dp);
+    int st = get_plan(N, M, P, Q, o.ring_cols, o.ring_rows, engine, &dp);
     if (st != COVEST_OK) return st;
     const ShapePlan &sp = dp->sp;
     if (ws_bytes < sp.ws_bytes || (sp.ws_bytes > 0 && ws == nullptr))
         return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", sp.ws_bytes, ws_bytes);
     const Inst in = make_inst(sp, A, lda, R, ldr, ws, o);
-    if (!sp.jobs.empty()) {
+    if (!sp.mjobs.empty()) {
+        MfmaArgs ma{};
+        ma.jobs = dp->d_mjobs;
+        ma.insts = nullptr;
+        ma.n_jobs = (int)sp.mjobs.size();
+        ma.xcd_remap = dp->xcd_remap;
+        ma.use_inline = 1;
+        ma.inst_inline = in;
+        HIP_TRY(timed("rec_mfma", stream, [&] {
+            return launch_rec_mfma(ma, sp.mt, sp.nt, (int)sp.mjobs.size(), sp.lds_main, stream);
+        }));
+    } else if (!sp.jobs.empty()) {
         MainArgs ma{};
         ma.jobs = dp->d_jobs;
         ma.groups = dp->d_groups;
@@ -764,7 +810,14 @@ int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q, const cove
     if (use_recurrence(o)) {
         if (P > kMaxWindow || Q > kMaxWindow)
             return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
-        *bytes = host_plan((int)N, (int)M, (int)P, (int)Q, o.ring_cols, o.ring_rows)->ws_bytes;
+        const int engine = pick_engine((int)N, (int)M, (int)P, (int)Q, o);
+        if (engine == 0)
+            return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine cannot run this shape");
+        *bytes = host_plan((int)N, (int)M, (int)P, (int)Q, o.ring_cols, o.ring_rows, engine)->ws_bytes;
+        // AUTO falls back to the vector engine for inputs too large for
+        // 32-bit offsets: cover both plans
+        if (engine == 2 && o.engine == COVEST_ENGINE_AUTO)
+            *bytes = std::max(*bytes, host_plan((int)N, (int)M, (int)P, (int)Q, 0, 0, 1)->ws_bytes);
         return ok();
     }
     const int prec = hankel_prec(o.prec);
@@ -1025,3 +1078,53 @@ int covest_timing_read(covest_timing_record *out, int cap)
 }
 
 }  // extern "C"
+
+extern "C" int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
+                                    covest_mfma_plan_info *out, int32_t *jobs, int32_t *items)
+{
+    try {
+        if (!out) return fail(COVEST_ERR_INVALID_ARG, "out is null");
+        int st = check_shape(N, M, P, Q);
+        if (st != COVEST_OK) return st;
+        if (P > kMaxWindow || Q > kMaxWindow || !mfma_fits((int)N, (int)M, (int)P, (int)Q))
+            return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine cannot run this shape");
+        const ShapePlan sp = make_mfma_plan((int)N, (int)M, (int)P, (int)Q, n_cu > 0 ? n_cu : 256);
+        std::memset(out, 0, sizeof(*out));
+        out->mt = sp.mt;
+        out->nt = sp.nt;
+        out->Rm0 = sp.Rm0;
+        out->Rm1 = sp.Rm1;
+        out->Cm0 = sp.Cm0;
+        out->Cm1 = sp.Cm1;
+        out->n_ir = sp.n_ir;
+        out->n_ic = sp.n_ic;
+        out->lag_stride = sp.lag_stride;
+        out->n_bulk = sp.n_bulk;
+        out->n_jobs = (int32_t)sp.mjobs.size();
+        out->n_items = (int32_t)sp.items.size();
+        out->zpieces = sp.zpieces;
+        out->ws_bytes = (int64_t)sp.ws_bytes;
+        out->lds_main = (int64_t)sp.lds_main;
+        out->lds_fin = (int64_t)sp.lds_fin;
+        out->main_products = sp.main_products;
+        out->fin_products = sp.fin_products;
+        if (jobs) {
+            for (size_t k = 0; k < sp.mjobs.size(); ++k) {
+                const MJob &j = sp.mjobs[k];
+                const int32_t row[16] = {j.inst, j.orient, j.kind, j.out, j.line0, j.line_end, j.b0, j.kg0,
+                                         j.b1, j.kg1, j.n_kg, j.pos_lo, j.pos_hi, j.k0, 0, 0};
+                std::memcpy(jobs + 16 * k, row, sizeof(row));
+            }
+        }
+        if (items) {
+            for (size_t k = 0; k < sp.items.size(); ++k) {
+                const FinItem &it = sp.items[k];
+                const int32_t row[5] = {it.inst, it.dr, it.dc, it.bulk0, it.bulk1};
+                std::memcpy(items + 5 * k, row, sizeof(row));
+            }
+        }
+        return ok();
+    } catch (const std::exception &e) {
+        return fail(COVEST_ERR_INVALID_ARG, "%s", e.what());
+    }
+}

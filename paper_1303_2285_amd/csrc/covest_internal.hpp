@@ -85,7 +85,7 @@ struct Inst {
     int out_fp64;             // R element: 1 complex128, 0 complex64
     int fill_full;            // 1: write the conjugate mirror too
     int normalize;            // 1: divide by K
-    int pad;
+    int zpieces;              // strip sums come in this many pieces: zr[piece][n_ir][lag]
 };
 
 // One finalize work item: a unique combination of one instance.
@@ -102,6 +102,52 @@ struct MainArgs {
     int n_jobs;
     int xcd_remap;     // 1: give each XCD a contiguous block of jobs
     int use_inline;    // 1: every job uses inst_inline (single-problem calls)
+    int pad;
+    Inst inst_inline;
+};
+
+// ---------------------------------------------------------------------------
+// Matrix-core form of the main pass.  For one first-factor line (a row of A in
+// orientation 0, a column in orientation 1) the sums over a range of positions
+// of every lag form a dense product:
+//     T[d1][d2] = sum_{c'} conj(B[line + d1][c']) * x[c' - d2],
+// with B = A (or A^T), c' the second factor's position and x the line itself,
+// zero outside the position range.  The first operand is a block of 16 lines
+// at one position (rows of B), the second a Toeplitz band of the line: both
+// are read straight from A, and every product is still formed exactly once.
+// A workgroup has kMWaves waves; wave w takes line line0 + kMWaves*blk + w of
+// every block blk it visits, so the waves of a workgroup read neighbouring
+// lines at the same positions.
+constexpr int kMWaves = 8;
+constexpr int kMThreads = 64 * kMWaves;
+
+enum MJobKind : int { kMBulk = 0, kMStrip = 1 };
+
+// One workgroup of the matrix-core main kernel.  It visits the (block,
+// k-group) pairs from (b0, kg0) up to, not including, (b1, kg1) in
+// lexicographic order; a k-group is 4 consecutive second-factor positions
+// starting at k0.  bulk: lines are middle lines, every wave's sums are added
+// into partial row `out`.  strip: one block (b0 == b1 == 0); each wave writes
+// its line's sums to z row out + (line - line0) (the piece is part of out).
+struct MJob {
+    int inst;
+    int orient;          // 0: lines are rows of A, 1: columns
+    int kind;            // MJobKind
+    int out;
+    int line0, line_end; // lines >= line_end are skipped
+    int b0, kg0, b1, kg1;
+    int n_kg;            // k-groups per line
+    int pos_lo, pos_hi;  // first-factor positions [pos_lo, pos_hi) on every line
+    int k0;              // second-factor position of k-group 0, lane 0
+    int pad0, pad1;
+};
+
+struct MfmaArgs {
+    const MJob *jobs;
+    const Inst *insts;
+    int n_jobs;
+    int xcd_remap;
+    int use_inline;
     int pad;
     Inst inst_inline;
 };

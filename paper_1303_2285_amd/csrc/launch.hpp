@@ -15,4 +15,7 @@ hipError_t launch_rec_persistent(const MainArgs &ma, unsigned int *counter, int 
 hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
                                hipStream_t stream);
 
+// Matrix-core main pass (rec_mfma.hip): mt x nt tiles of the orientation-0 lag block.
+hipError_t launch_rec_mfma(const MfmaArgs &ma, int mt, int nt, int n_blocks, size_t lds, hipStream_t stream);
+
 }  // namespace covest

@@ -76,6 +76,50 @@ std::vector<int> ring_width_candidates(int n)
     return c;
 }
 
+// Finalize items (every unique combination, eq. 3.3, in lag-index order,
+// dr-major, so that neighbouring items read neighbouring partial sums), the
+// finalize variant, the workspace size and the product counts.
+template <class BulkRange>
+static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
+{
+    const int N = sp.N, M = sp.M, P = sp.P, Q = sp.Q;
+    for (int dr = -(P - 1); dr < P; ++dr) {
+        for (int dc = (dr < 0 ? 1 : 0); dc < Q; ++dc) {
+            FinItem it{};
+            it.inst = 0;
+            it.dr = dr;
+            it.dc = dc;
+            it.bulk0 = it.bulk1 = 0;
+            bulk_range(dr, dc, it);
+            sp.items.push_back(it);
+        }
+    }
+    const size_t table = (size_t)(1 + sp.n_ir) * (sp.n_ic | 1) * 16;
+    sp.fin_table = table <= kFinTableMax;
+    sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
+
+    sp.ws_bytes = (size_t)16 * sp.lag_stride *
+                  ((size_t)sp.n_bulk + (size_t)sp.zpieces * ((size_t)sp.n_ir + (size_t)sp.n_ic));
+
+    // Product counts (for throughput figures): the finalize computes the
+    // corner products (individual row and individual column) of every lag, the
+    // main kernel all the others.
+    const Counts cnt = method_counts(N, M, P, Q);
+    int64_t corner = 0;
+    for (int dc = 0; dc < Q; ++dc) {
+        for (int dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
+            const int rlo = std::max(0, -dr), rhi = N - std::max(0, dr);
+            const int chi = M - dc;
+            int64_t rows = 0, cols = 0;
+            for (int r = rlo; r < rhi; ++r) rows += (r < sp.Rm0 || r >= sp.Rm1) ? 1 : 0;
+            for (int c = 0; c < chi; ++c) cols += (c < sp.Cm0 || c >= sp.Cm1) ? 1 : 0;
+            corner += rows * cols;
+        }
+    }
+    sp.fin_products = corner;
+    sp.main_products = cnt.um - corner;
+}
+
 ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0, int w1)
 {
     ShapePlan sp;
@@ -237,50 +281,139 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0, int w
         sp.lds_main = std::max(sp.lds_main, tile_bytes(rows, tc + halo_c));
     }
 
-    // Finalize items: every unique combination (eq. 3.3), in lag-index order
-    // (dr-major) so that neighbouring items read neighbouring partial sums.
-    for (int dr = -(P - 1); dr < P; ++dr) {
-        for (int dc = (dr < 0 ? 1 : 0); dc < Q; ++dc) {
-            FinItem it{};
-            it.inst = 0;
-            it.dr = dr;
-            it.dc = dc;
-            it.bulk0 = it.bulk1 = 0;
-            for (size_t k = 0; k < g0.size(); ++k) {
-                const LagGroup &g = sp.groups[g0[k]];
-                const bool in_type = (dr >= 0) == (g.d1lo >= 0);
-                if (in_type && dr >= g.d1lo && dr < g.d1hi && njob[k] > 0) {
-                    it.bulk0 = out_base[k];
-                    it.bulk1 = out_base[k] + njob[k];
-                }
+    finish_plan(sp, [&](int dr, int dc, FinItem &it) {
+        for (size_t k = 0; k < g0.size(); ++k) {
+            const LagGroup &g = sp.groups[g0[k]];
+            const bool in_type = (dr >= 0) == (g.d1lo >= 0);
+            if (in_type && dr >= g.d1lo && dr < g.d1hi && njob[k] > 0) {
+                it.bulk0 = out_base[k];
+                it.bulk1 = out_base[k] + njob[k];
             }
-            sp.items.push_back(it);
+        }
+    });
+    return sp;
+}
+
+
+bool mfma_fits(int N, int M, int P, int Q)
+{
+    if (N - 2 * P + 2 < 1 || M - 2 * Q + 2 < 1) return false;
+    const int mt = (2 * P - 1 + 15) / 16, nt = (Q + 15) / 16;
+    if (mt * nt > 8) return false;
+    return (double)(2 * P - 1) * Q >= 0.7 * 256.0 * mt * nt;
+}
+
+ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
+{
+    ShapePlan sp;
+    sp.engine = 2;
+    sp.N = N;
+    sp.M = M;
+    sp.P = P;
+    sp.Q = Q;
+    sp.mt = (2 * P - 1 + 15) / 16;
+    sp.nt = (Q + 15) / 16;
+    sp.lag_stride = (2 * P - 1) * Q;
+    sp.Rm0 = P - 1;
+    sp.Rm1 = N - P + 1;
+    sp.Cm0 = Q - 1;
+    sp.Cm1 = M - Q + 1;
+    sp.n_ir = N - (sp.Rm1 - sp.Rm0);
+    sp.n_ic = M - (sp.Cm1 - sp.Cm0);
+    n_cu = std::max(1, n_cu);
+
+    // Positions a line walks: orientation 0 (rows) has first-factor columns
+    // [Cm0, Cm1) and lags dc in [0, Q); orientation 1 (columns) has first-factor
+    // rows [Rm0, Rm1) and lags dr in (-P, P).
+    const int nkg[2] = {(sp.Cm1 - sp.Cm0 + Q - 1 + 3) / 4, (sp.Rm1 - sp.Rm0 + 2 * (P - 1) + 3) / 4};
+    const int plo[2] = {sp.Cm0, sp.Rm0}, phi[2] = {sp.Cm1, sp.Rm1};
+    const int k0[2] = {sp.Cm0, sp.Rm0 - (P - 1)};
+
+    struct StripBlock { int orient, line0, line_end, zrow0; };
+    std::vector<StripBlock> sbs;
+    auto add_side = [&](int orient, int lo, int hi, int zbase) {
+        for (int l = lo; l < hi; l += kMWaves) sbs.push_back({orient, l, std::min(hi, l + kMWaves), zbase + (l - lo)});
+    };
+    add_side(0, 0, sp.Rm0, 0);
+    add_side(0, sp.Rm1, N, sp.Rm0);
+    add_side(1, 0, sp.Cm0, 0);
+    add_side(1, sp.Cm1, M, sp.Cm0);
+
+    const int nblk = (sp.Rm1 - sp.Rm0 + kMWaves - 1) / kMWaves;
+    const int64_t U = (int64_t)nblk * nkg[0];
+    double strip_total = 0.0;
+    int strip_len = 0, strip_min = 1 << 30;
+    for (const StripBlock &b : sbs) {
+        strip_total += nkg[b.orient];
+        strip_len = std::max(strip_len, nkg[b.orient]);
+        strip_min = std::min(strip_min, nkg[b.orient]);
+    }
+    const double ideal = ((double)U + strip_total) / n_cu;
+    // pieces per strip line: a piece no longer than a balanced share, and no
+    // piece empty (the finalize adds every piece's row, so each is written)
+    sp.zpieces = 1;
+    if (strip_len > 0) {
+        const double want = std::ceil(strip_len / ideal - 1e-9);
+        sp.zpieces = (int)std::max(1.0, std::min({8.0, want, (double)strip_min}));
+    }
+
+    int smax = 0;
+    std::vector<MJob> strips;
+    for (const StripBlock &b : sbs) {
+        const int o = b.orient, nk = nkg[o];
+        for (int p = 0; p < sp.zpieces; ++p) {
+            MJob j{};
+            j.orient = o;
+            j.kind = kMStrip;
+            j.out = p * (o ? sp.n_ic : sp.n_ir) + b.zrow0;
+            j.line0 = b.line0;
+            j.line_end = b.line_end;
+            j.b0 = j.b1 = 0;
+            j.kg0 = (int)((int64_t)nk * p / sp.zpieces);
+            j.kg1 = (int)((int64_t)nk * (p + 1) / sp.zpieces);
+            j.n_kg = nk;
+            j.pos_lo = plo[o];
+            j.pos_hi = phi[o];
+            j.k0 = k0[o];
+            strips.push_back(j);
+            smax = std::max(smax, j.kg1 - j.kg0);
         }
     }
-    const size_t table = (size_t)(1 + sp.n_ir) * (sp.n_ic | 1) * 16;
-    sp.fin_table = table <= kFinTableMax;
-    sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
 
-    sp.ws_bytes = (size_t)16 * sp.lag_stride *
-                  ((size_t)sp.n_bulk + (size_t)sp.n_ir + (size_t)sp.n_ic);
-
-    // Product counts (for throughput figures): the finalize computes the
-    // corner products (individual row and individual column) of every lag, the
-    // main kernel all the others.
-    const Counts cnt = method_counts(N, M, P, Q);
-    int64_t corner = 0;
-    for (int dc = 0; dc < Q; ++dc) {
-        for (int dr = (dc == 0 ? 0 : -(P - 1)); dr < P; ++dr) {
-            const int rlo = std::max(0, -dr), rhi = N - std::max(0, dr);
-            const int chi = M - dc;
-            int64_t rows = 0, cols = 0;
-            for (int r = rlo; r < rhi; ++r) rows += (r < sp.Rm0 || r >= sp.Rm1) ? 1 : 0;
-            for (int c = 0; c < chi; ++c) cols += (c < sp.Cm0 || c >= sp.Cm1) ? 1 : 0;
-            corner += rows * cols;
-        }
+    const int n_strip = (int)strips.size();
+    int n_bulk;
+    if (n_strip < n_cu && smax <= 1.1 * ideal) n_bulk = n_cu - n_strip;
+    else n_bulk = (int)std::ceil((double)U / std::max((double)smax, ideal));
+    n_bulk = (int)std::max<int64_t>(1, std::min<int64_t>(n_bulk, std::max<int64_t>(1, U / 4)));
+    sp.n_bulk = n_bulk;
+    for (int j = 0; j < n_bulk; ++j) {
+        const int64_t u0 = U * j / n_bulk, u1 = U * (j + 1) / n_bulk;
+        MJob b{};
+        b.orient = 0;
+        b.kind = kMBulk;
+        b.out = j;
+        b.line0 = sp.Rm0;
+        b.line_end = sp.Rm1;
+        b.b0 = (int)(u0 / nkg[0]);
+        b.kg0 = (int)(u0 % nkg[0]);
+        b.b1 = (int)(u1 / nkg[0]);
+        b.kg1 = (int)(u1 % nkg[0]);
+        b.n_kg = nkg[0];
+        b.pos_lo = plo[0];
+        b.pos_hi = phi[0];
+        b.k0 = k0[0];
+        sp.mjobs.push_back(b);
+        sp.job_cost.push_back((double)(u1 - u0));
     }
-    sp.fin_products = corner;
-    sp.main_products = cnt.um - corner;
+    for (const MJob &j : strips) {
+        sp.mjobs.push_back(j);
+        sp.job_cost.push_back((double)(j.kg1 - j.kg0));
+    }
+    sp.lds_main = (size_t)4 * 8 * sp.mt * sp.nt * 64 * sizeof(double);
+    finish_plan(sp, [&](int, int, FinItem &it) {
+        it.bulk0 = 0;
+        it.bulk1 = sp.n_bulk;
+    });
     return sp;
 }
 

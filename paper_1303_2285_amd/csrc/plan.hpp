@@ -24,6 +24,7 @@ Counts method_counts(int64_t N, int64_t M, int64_t P, int64_t Q);
 // Plan of one problem shape.  Job::inst is 0, outputs are relative to this
 // shape's own workspace; batched plans offset them.
 struct ShapePlan {
+    int engine = 1;                      // 1: vector ring walk (rec_main), 2: matrix cores (rec_mfma)
     int N = 0, M = 0, P = 0, Q = 0;
     int W0 = 0, W1 = 0;
     int Rm0 = 0, Rm1 = 0, Cm0 = 0, Cm1 = 0, n_ir = 0, n_ic = 0;
@@ -38,11 +39,23 @@ struct ShapePlan {
     size_t ws_bytes = 0;                 // partial + zr + zc, FP64 complex
     int64_t main_products = 0;           // distinct products the main kernel keeps
     int64_t fin_products = 0;            // corner products the finalize computes
+    // matrix-core engine only
+    int mt = 0, nt = 0;                  // 16 x 16 tiles of the orientation-0 lag block (d1 = dr, d2 = dc)
+    int zpieces = 1;                     // pieces per strip line
+    std::vector<MJob> mjobs;
 };
 
 // n_slots: workgroups resident at once on the target device (2 per CU).
 // w0 / w1 override the ring widths along columns / rows (0: the default choice).
 ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0 = 0, int w1 = 0);
+
+// Matrix-core plan: one workgroup of kMWaves waves per compute unit (n_cu).
+// Valid when mfma_fits(N, M, P, Q).
+ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu);
+
+// The matrix-core engine needs a non-empty middle block, a lag block of at
+// most 8 tiles (one wave holds all its sums) and little tile padding.
+bool mfma_fits(int N, int M, int P, int Q);
 
 // Ring widths worth trying for a window extent n (the first is the default).
 std::vector<int> ring_width_candidates(int n);

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "covest_internal.hpp"
+#include "device_util.hpp"
 
 namespace covest {
 
@@ -46,6 +47,15 @@ __device__ __forceinline__ double2 cprod(const double2 x, const double2 y)
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// Strip sum of individual row (or column) idx for one lag: the pieces of the
+// strip, added in piece order.
+__device__ __forceinline__ double2 zsum(const double2 *z, int idx, int nrows, int pieces, int64_t ls2, int lag)
+{
+    double2 s = z[(int64_t)idx * ls2 + lag];
+    for (int p = 1; p < pieces; ++p) s = cadd(s, z[((int64_t)p * nrows + idx) * ls2 + lag]);
+    return s;
+}
 
 __device__ __forceinline__ double2 ld_a(const Inst &in, int r, int c)
 {
@@ -218,16 +228,6 @@ __device__ void run_strip(const Job &job, const Inst &in, const LagGroup &g, dou
     }
 }
 
-// Workgroup b of a launch runs on XCD b % 8.  Map the workgroups of one XCD
-// to one contiguous range of the work list (any n), so that neighbouring work
-// items (jobs over one region of A, or finalize items of neighbouring lags,
-// whose partial sums share cache lines) meet in the same L2.
-__device__ __forceinline__ int xcd_block(int b, int n)
-{
-    const int x = b & 7;
-    return x * (n >> 3) + min(x, n & 7) + (b >> 3);
-}
-
 __device__ __forceinline__ void run_job(const MainArgs &ma, int b, double2 *lds)
 {
     const Job job = ma.jobs[b];
@@ -332,6 +332,8 @@ __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
     const double2 *partial = reinterpret_cast<const double2 *>(in.partial);
     const double2 *zr = reinterpret_cast<const double2 *>(in.zr);
     const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
+#define ZR(i) zsum(zr, (i), in.n_ir, in.zpieces, ls2, lag)
+#define ZC(i) zsum(zc, (i), in.n_ic, in.zpieces, ls2, lag)
     const bool has_mr = Rm1 > Rm0;   // column strips exist (they walk the middle rows)
     const bool has_mc = Cm1 > Cm0;   // row strips exist (they walk the middle columns)
 
@@ -352,20 +354,20 @@ __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
                 continue;
             }
             double2 s = zm;
-            for (int c = 0; c < min(Cm0, Kc); ++c) s = cadd(s, zc[c * ls2 + lag]);
-            for (int c = Cm1; c < Kc; ++c) s = cadd(s, zc[(Cm0 + c - Cm1) * ls2 + lag]);
+            for (int c = 0; c < min(Cm0, Kc); ++c) s = cadd(s, ZC(c));
+            for (int c = Cm1; c < Kc; ++c) s = cadd(s, ZC(Cm0 + c - Cm1));
             out[0] = s;
             for (int b = 0; b + 1 < nc; ++b) {
                 const int cin = b + Kc;   // enters: an individual column >= Cm1
-                s = csub(s, zc[b * ls2 + lag]);
-                s = cadd(s, zc[(Cm0 + cin - Cm1) * ls2 + lag]);
+                s = csub(s, ZC(b));
+                s = cadd(s, ZC(Cm0 + cin - Cm1));
                 out[b + 1] = s;
             }
         } else {
             const int rho = e - 1;
             const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
             if (r < rlo || r >= rhi) continue;
-            double2 s = has_mc ? zr[rho * ls2 + lag] : make_double2(0.0, 0.0);
+            double2 s = has_mc ? ZR(rho) : make_double2(0.0, 0.0);
             for (int c = 0; c < min(Cm0, Kc); ++c) s = cadd(s, cprod(ld_a(in, r, c), ld_a(in, r + dr, c + dc)));
             for (int c = Cm1; c < Kc; ++c) s = cadd(s, cprod(ld_a(in, r, c), ld_a(in, r + dr, c + dc)));
             out[0] = s;
@@ -423,6 +425,8 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     const double2 *partial = reinterpret_cast<const double2 *>(in.partial);
     const double2 *zr = reinterpret_cast<const double2 *>(in.zr);
     const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
+#define ZR(i) zsum(zr, (i), in.n_ir, in.zpieces, ls2, lag)
+#define ZC(i) zsum(zc, (i), in.n_ic, in.zpieces, ls2, lag)
     const float2 *A = static_cast<const float2 *>(in.A);
     const int nV = in.n_ic;
     const int nVs = nV | 1;   // odd row stride: no LDS bank conflicts across rows
@@ -446,7 +450,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
         double2 v = make_double2(0.0, 0.0);
         if (c + dc < M) {
             if (cls == 0) {
-                if (has_mr) v = zc[gi * ls2 + lag];
+                if (has_mr) v = ZC(gi);
             } else {
                 const int rho = cls - 1;
                 const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
@@ -483,7 +487,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
             const double2 *row = V + cls * nVs;
             double2 s;
             if (cls == 0) s = has_mr ? zm : make_double2(0.0, 0.0);
-            else s = has_mc ? zr[(cls - 1) * ls2 + lag] : make_double2(0.0, 0.0);
+            else s = has_mc ? ZR(cls - 1) : make_double2(0.0, 0.0);
             // columns [b0, b0 + Kc) of the individual set: left part, right part
             for (int gi = b0; gi < min(Cm0, b0 + Kc); ++gi) s = cadd(s, row[gi]);
             for (int c = max(Cm1, b0); c < b0 + Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);
@@ -527,6 +531,9 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
         }
     }
 }
+
+#undef ZR
+#undef ZC
 
 // ---------------------------------------------------------------------------
 // Host launch helpers

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert cv.version() == 1
+    assert cv.version() == 2
 
 
 def _opts(**kw):
@@ -57,6 +57,19 @@ def test_workspace_query_errors():
         == cv.ERR_UNSUPPORTED
     bad = cv.make_opts(ring_cols=6)
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
+    bad = cv.make_opts()
+    bad.engine = 3
+    assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
+    assert "engine" in L.covest_last_error().decode()
+    # the matrix-core engine: not for an 8 x 8 window; its own plan for 32 x 32
+    assert L.covest_workspace_size(64, 64, 8, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(engine="matrix"), ctypes.byref(n)) == cv.OK
+    assert n.value == cv.mfma_plan(1024, 1024, 32, 32)[0]["ws_bytes"]
+    assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(engine="vector"), ctypes.byref(n)) == cv.OK
+    assert n.value == cv.plan_info(1024, 1024, 32, 32)["ws_bytes"]
+    m = ctypes.c_size_t(0)
+    assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(), ctypes.byref(m)) == cv.OK
+    assert m.value == max(n.value, cv.mfma_plan(1024, 1024, 32, 32)[0]["ws_bytes"])
     assert L.covest_workspace_size(64, 64, 8, 8, None, ctypes.byref(n)) == cv.OK
     assert n.value == cv.plan_info(64, 64, 8, 8)["ws_bytes"]
 

@@ -227,24 +227,23 @@ def test_plan_cfg3_fills_the_gpu():
 # The decomposition itself, modelled on the CPU
 # ---------------------------------------------------------------------------
 
-def model_forward(A, P, Q, info):
-    """R from middle sums, strip sums, corner products and sliding boxes."""
+def model_finalize(A, P, Q, info, sums):
+    """R from the middle, strip and corner sums by sliding boxes (the finalize).
+
+    sums(dr, dc) -> (zm, zr, zc): the middle sum, {individual row: sum over
+    the middle columns} and {individual column: sum over the middle rows}."""
     A = np.asarray(A, dtype=np.complex128)
     N, M = A.shape
     Kr, Kc = N - P + 1, M - Q + 1
     Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
     ind_r = [r for r in range(N) if r < Rm0 or r >= Rm1]
     ind_c = [c for c in range(M) if c < Cm0 or c >= Cm1]
-    rho = {r: i for i, r in enumerate(ind_r)}
-    gam = {c: i for i, c in enumerate(ind_c)}
     R = np.zeros((P * Q, P * Q), dtype=np.complex128)
     for dr, dc in uc_set(P, Q):
         Pi = np.zeros((N, M), dtype=np.complex128)
         r0, r1 = max(0, -dr), N - max(0, dr)
         Pi[r0:r1, :M - dc] = A[r0:r1, :M - dc] * A[r0 + dr:r1 + dr, dc:].conj()
-        zm = Pi[Rm0:Rm1, Cm0:Cm1].sum()
-        zr = {r: Pi[r, Cm0:Cm1].sum() for r in ind_r}
-        zc = {c: Pi[Rm0:Rm1, c].sum() for c in ind_c}
+        zm, zr, zc = sums(dr, dc)
         nr, nc = P - abs(dr), Q - dc
         rlo = max(0, -dr)
         cs = {}
@@ -273,6 +272,24 @@ def model_forward(A, P, Q, info):
     return R
 
 
+def model_forward(A, P, Q, info):
+    """R from middle sums, strip sums, corner products and sliding boxes."""
+    A = np.asarray(A, dtype=np.complex128)
+    N, M = A.shape
+    Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
+
+    def sums(dr, dc):
+        Pi = np.zeros((N, M), dtype=np.complex128)
+        r0, r1 = max(0, -dr), N - max(0, dr)
+        Pi[r0:r1, :M - dc] = A[r0:r1, :M - dc] * A[r0 + dr:r1 + dr, dc:].conj()
+        zm = Pi[Rm0:Rm1, Cm0:Cm1].sum()
+        zr = {r: Pi[r, Cm0:Cm1].sum() for r in range(N) if r < Rm0 or r >= Rm1}
+        zc = {c: Pi[Rm0:Rm1, c].sum() for c in range(M) if c < Cm0 or c >= Cm1}
+        return zm, zr, zc
+
+    return model_finalize(A, P, Q, info, sums)
+
+
 @pytest.mark.parametrize("shape", [(64, 64, 8, 8), (40, 33, 4, 16), (9, 9, 5, 5), (6, 7, 6, 7),
                                    (130, 64, 3, 1), (20, 20, 1, 1), (72, 70, 12, 4)])
 def test_decomposition_reproduces_oracle(oracle_mod, shape):
@@ -288,3 +305,166 @@ def test_decomposition_reproduces_oracle(oracle_mod, shape):
     ref = oracle_mod.forward(A, P, Q)
     assert np.array_equal(R.real, ref.real)
     assert np.array_equal(R.imag, ref.imag)
+
+
+# ---------------------------------------------------------------------------
+# The matrix-core engine's plan: ownership and a model of its kernel
+# ---------------------------------------------------------------------------
+
+MFMA_SHAPES = [(1024, 1024, 32, 32), (256, 256, 16, 16), (512, 512, 16, 16), (40, 36, 16, 16),
+               (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16), (34, 64, 16, 32), (300, 64, 28, 28)]
+
+
+def test_mfma_fits():
+    for shape in [(1024, 1024, 32, 32), (256, 256, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16)]:
+        cv.mfma_plan(*shape)
+    for shape in [(64, 64, 8, 8), (256, 256, 12, 12), (300, 300, 48, 48), (30, 40, 16, 16), (40, 30, 16, 16)]:
+        with pytest.raises(cv.CovestError) as e:
+            cv.mfma_plan(*shape)
+        assert e.value.status == cv.ERR_UNSUPPORTED, shape
+
+
+def mfma_visits(job):
+    """(line, k-group) pairs a job covers, per wave."""
+    inst, o, kind, out, line0, line_end, b0, kg0, b1, kg1, nkg = job[:11]
+    for bl in range(b0, b1 + 1):
+        kga = kg0 if bl == b0 else 0
+        kgb = kg1 if bl == b1 else nkg
+        for w in range(8):
+            line = line0 + 8 * bl + w
+            if kga < kgb and line < line_end:
+                for kg in range(kga, kgb):
+                    yield w, line, kg
+
+
+@pytest.mark.parametrize("shape", MFMA_SHAPES)
+@pytest.mark.parametrize("n_cu", [256, 16, 3, 1])
+def test_mfma_plan_ownership(shape, n_cu):
+    N, M, P, Q = shape
+    info, jobs, items = cv.mfma_plan(N, M, P, Q, n_cu)
+    assert (info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]) == (P - 1, N - P + 1, Q - 1, M - Q + 1)
+    assert info["mt"] == -(-(2 * P - 1) // 16) and info["nt"] == -(-Q // 16)
+    nkg = {0: -(-(info["Cm1"] - info["Cm0"] + Q - 1) // 4), 1: -(-(info["Rm1"] - info["Rm0"] + 2 * (P - 1)) // 4)}
+    ind = {0: [r for r in range(N) if r < info["Rm0"] or r >= info["Rm1"]],
+           1: [c for c in range(M) if c < info["Cm0"] or c >= info["Cm1"]]}
+    zp = info["zpieces"]
+    bulk = {}
+    strip = {0: {}, 1: {}}
+    bulk_outs = []
+    for j in jobs:
+        o, kind, out, line0 = int(j[1]), int(j[2]), int(j[3]), int(j[4])
+        assert j[10] == nkg[o]
+        assert (j[11], j[12]) == ((info["Cm0"], info["Cm1"]) if o == 0 else (info["Rm0"], info["Rm1"]))
+        assert j[13] == (info["Cm0"] if o == 0 else info["Rm0"] - (P - 1))
+        if kind == 0:
+            assert o == 0 and (j[4], j[5]) == (info["Rm0"], info["Rm1"])
+            bulk_outs.append(out)
+            for w, line, kg in mfma_visits(j):
+                bulk[(line, kg)] = bulk.get((line, kg), 0) + 1
+        else:
+            assert j[6] == j[8] == 0 and j[5] - j[4] <= 8
+            # every piece of every strip line is written (the finalize adds them all)
+            assert j[9] > j[7]
+            for w, line, kg in mfma_visits(j):
+                zrow = out + (line - line0)
+                piece, idx = divmod(zrow, len(ind[o]))
+                assert piece < zp and ind[o][idx] == line
+                key = (line, kg)
+                assert key not in strip[o]
+                strip[o][key] = piece
+    assert sorted(bulk_outs) == list(range(info["n_bulk"]))
+    want = {(l, k) for l in range(info["Rm0"], info["Rm1"]) for k in range(nkg[0])}
+    assert set(bulk) == want and all(v == 1 for v in bulk.values())
+    for o in (0, 1):
+        assert set(strip[o]) == {(l, k) for l in ind[o] for k in range(nkg[o])}
+        # pieces cover consecutive k-groups in piece order
+        for l in ind[o]:
+            ps = [strip[o][(l, k)] for k in range(nkg[o])]
+            assert ps == sorted(ps)
+    assert sorted((int(i[1]), int(i[2])) for i in items) == sorted(uc_set(P, Q))
+    assert all(i[3] == 0 and i[4] == info["n_bulk"] for i in items)
+    c = cv.counts(N, M, P, Q)
+    assert info["main_products"] + info["fin_products"] == c["um"]
+    if n_cu == 256 and N * M >= 256 * 256:
+        assert len(jobs) <= 256
+        # cost of a job: (block, k-group) steps, its waves running side by side
+        cost = [len({((line - j[4]) // 8, kg) for w, line, kg in mfma_visits(j)}) for j in jobs]
+        assert max(cost) <= 1.15 * (sum(cost) / 256) + 1   # balanced to a few percent
+
+
+def mfma_model_sums(A, P, Q, info, jobs):
+    """What the matrix-core kernel computes, in NumPy: per job, the products of
+    a block of lines (rows of A, or of A^T) with the Toeplitz band of the line,
+    at clamped indices, summed over its k-groups; then the sums the finalize
+    reads (bulk partials added, strip pieces added)."""
+    A = np.asarray(A, dtype=np.complex128)
+    N, M = A.shape
+    mt, nt, zp = info["mt"], info["nt"], info["zpieces"]
+    L = info["lag_stride"]
+    # the workspace starts as garbage (NaN here): every sum the finalize reads
+    # must have been written
+    partial = np.full((info["n_bulk"], L), np.nan, dtype=np.complex128)
+    z = {0: np.full((zp * info["n_ir"], L), np.nan, dtype=np.complex128),
+         1: np.full((zp * info["n_ic"], L), np.nan, dtype=np.complex128)}
+
+    def lag_rows(o, tm, tn):
+        d1 = (0 if o else -(P - 1)) + np.arange(16 * tm)
+        d2 = (-(P - 1) if o else 0) + np.arange(16 * tn)
+        return d1, d2
+
+    def store(row, o, d1, d2, T):
+        for a, v1 in enumerate(d1):
+            for b, v2 in enumerate(d2):
+                dr, dc = (v2, v1) if o else (v1, v2)
+                if 0 <= dc < Q and -P < dr < P and (dc > 0 or dr >= 0):
+                    row[(dr + P - 1) * Q + dc] = T[a, b]
+
+    for j in jobs:
+        o, kind, out, line0, line_end, b0, kg0, b1, kg1, nkg, plo, phi, k0 = [int(v) for v in j[1:14]]
+        B = A.T if o else A
+        nlines, npos = B.shape
+        tm, tn = (nt, mt) if o else (mt, nt)
+        d1, d2 = lag_rows(o, tm, tn)
+        acc = np.zeros((16 * tm, 16 * tn), dtype=np.complex128)
+        for bl in range(b0, b1 + 1):
+            kga = kg0 if bl == b0 else 0
+            kgb = kg1 if bl == b1 else nkg
+            for w in range(8):
+                line = line0 + 8 * bl + w
+                if kga >= kgb or line >= line_end:
+                    continue
+                cps = np.arange(k0 + 4 * kga, k0 + 4 * kgb)
+                Y = B[np.clip(line + d1, 0, nlines - 1)][:, np.minimum(cps, npos - 1)]
+                xp = cps[None, :] - d2[:, None]
+                X = np.where((xp >= plo) & (xp < phi), B[line][np.clip(xp, 0, npos - 1)], 0)
+                T = Y.conj() @ X.T
+                if kind == 1:
+                    store(z[o][out + line - line0], o, d1, d2, T)
+                else:
+                    acc += T
+        if kind == 0:
+            store(partial[out], o, d1, d2, acc)
+    Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
+    ind_r = [r for r in range(N) if r < Rm0 or r >= Rm1]
+    ind_c = [c for c in range(M) if c < Cm0 or c >= Cm1]
+
+    def sums(dr, dc):
+        lag = (dr + P - 1) * Q + dc
+        zm = partial[:, lag].sum()
+        zr = {r: sum(z[0][p * len(ind_r) + i, lag] for p in range(zp)) for i, r in enumerate(ind_r)}
+        zc = {c: sum(z[1][p * len(ind_c) + i, lag] for p in range(zp)) for i, c in enumerate(ind_c)}
+        return zm, zr, zc
+
+    return sums
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 16, 16), (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16),
+                                   (34, 64, 16, 32)])
+@pytest.mark.parametrize("n_cu", [256, 5])
+def test_mfma_model_reproduces_oracle(oracle_mod, shape, n_cu):
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=3 * N + M)
+    info, jobs, items = cv.mfma_plan(N, M, P, Q, n_cu)
+    R = model_finalize(A, P, Q, info, mfma_model_sums(A, P, Q, info, jobs))
+    ref = oracle_mod.forward(A, P, Q)
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
