@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
     ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
+    ap.add_argument("--no-vector", action="store_true",
+                    help="skip the comparison run of the recurrence on the vector engine")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 256 MiB (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
@@ -255,7 +257,7 @@ def main():
 
     # The other engine of the recurrence on the same input, for comparison.
     vec = None
-    if engine == "matrix":
+    if engine == "matrix" and not args.no_vector:
         wsv = torch.empty(max(1, covest.workspace_size(N, M, P, Q, engine="vector")), dtype=torch.uint8,
                           device=dev)
         Rv = torch.empty_like(R)

@@ -302,11 +302,9 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     if (!sp.mjobs.empty()) {
         MfmaArgs ma{};
         ma.jobs = dp->d_mjobs;
-        ma.insts = nullptr;
         ma.n_jobs = (int)sp.mjobs.size();
         ma.xcd_remap = dp->xcd_remap;
-        ma.use_inline = 1;
-        ma.inst_inline = in;
+        ma.inst = in;
         HIP_TRY(timed("rec_mfma", stream, [&] {
             return launch_rec_mfma(ma, sp.mt, sp.nt, (int)sp.mjobs.size(), sp.lds_main, stream);
         }));

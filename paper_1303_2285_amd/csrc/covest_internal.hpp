@@ -120,6 +120,7 @@ struct MainArgs {
 // lines at the same positions.
 constexpr int kMWaves = 8;
 constexpr int kMThreads = 64 * kMWaves;
+constexpr int kMXCap = 2048;   // first factors staged per wave (float2), orientation 0
 
 enum MJobKind : int { kMBulk = 0, kMStrip = 1 };
 
@@ -142,14 +143,13 @@ struct MJob {
     int pad0, pad1;
 };
 
+// The problem descriptor travels in the kernel arguments, so that its fields
+// (and everything derived from them) stay in scalar registers.
 struct MfmaArgs {
     const MJob *jobs;
-    const Inst *insts;
     int n_jobs;
     int xcd_remap;
-    int use_inline;
-    int pad;
-    Inst inst_inline;
+    Inst inst;
 };
 
 struct FinArgs {

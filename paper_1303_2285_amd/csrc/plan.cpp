@@ -297,7 +297,7 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0, int w
 
 bool mfma_fits(int N, int M, int P, int Q)
 {
-    if (N - 2 * P + 2 < 1 || M - 2 * Q + 2 < 1) return false;
+    if (N - 2 * P + 2 < 1 || M - 2 * Q + 2 < 1 || Q < 4) return false;
     const int mt = (2 * P - 1 + 15) / 16, nt = (Q + 15) / 16;
     if (mt * nt > 8) return false;
     return (double)(2 * P - 1) * Q >= 0.7 * 256.0 * mt * nt;
@@ -327,7 +327,10 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
     // rows [Rm0, Rm1) and lags dr in (-P, P).
     const int nkg[2] = {(sp.Cm1 - sp.Cm0 + Q - 1 + 3) / 4, (sp.Rm1 - sp.Rm0 + 2 * (P - 1) + 3) / 4};
     const int plo[2] = {sp.Cm0, sp.Rm0}, phi[2] = {sp.Cm1, sp.Rm1};
-    const int k0[2] = {sp.Cm0, sp.Rm0 - (P - 1)};
+    // Orientation 0 ends its k-groups at the last column of A (it reads its
+    // first operand unchecked), starting up to 3 positions before Cm0: those
+    // positions only meet first factors outside [Cm0, Cm1), which are zero.
+    const int k0[2] = {sp.Cm1 + Q - 1 - 4 * nkg[0], sp.Rm0 - (P - 1)};
 
     struct StripBlock { int orient, line0, line_end, zrow0; };
     std::vector<StripBlock> sbs;
@@ -409,7 +412,8 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
         sp.mjobs.push_back(j);
         sp.job_cost.push_back((double)(j.kg1 - j.kg0));
     }
-    sp.lds_main = (size_t)4 * 8 * sp.mt * sp.nt * 64 * sizeof(double);
+    sp.lds_main = std::max((size_t)4 * 8 * sp.mt * sp.nt * 64 * sizeof(double),
+                           (size_t)kMWaves * kMXCap * 8);
     finish_plan(sp, [&](int, int, FinItem &it) {
         it.bulk0 = 0;
         it.bulk1 = sp.n_bulk;

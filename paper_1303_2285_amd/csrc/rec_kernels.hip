@@ -443,25 +443,38 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     }
     const double2 zm = red[0];
 
-    // Phase A: the table of individual-column terms of every row class.
-    for (int e = tid; e < ncls * nV; e += 256) {
-        const int cls = e / nV, gi = e - cls * nV;
+    // Phase A: the table of individual-column terms of every row class.  The
+    // column-strip sums (class 0) come first; then the corner products, whose
+    // loads are issued kFinBatch at a time before any is used, so that their
+    // latencies overlap.
+    for (int gi = tid; gi < nV; gi += 256) {
         const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
-        double2 v = make_double2(0.0, 0.0);
-        if (c + dc < M) {
-            if (cls == 0) {
-                if (has_mr) v = ZC(gi);
-            } else {
-                const int rho = cls - 1;
-                const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
-                if (r >= rlo && r < rhi) {
-                    const float2 x = A[(int64_t)r * in.lda + c];
-                    const float2 y = A[(int64_t)(r + dr) * in.lda + c + dc];
-                    v = cprod(make_double2(x.x, x.y), make_double2(y.x, y.y));
-                }
-            }
+        V[gi] = (has_mr && c + dc < M) ? ZC(gi) : make_double2(0.0, 0.0);
+    }
+    constexpr int kFinBatch = 8;
+    const int ncorner = (ncls - 1) * nV;
+    for (int e0 = tid; e0 < ncorner; e0 += kFinBatch * 256) {
+        float2 xs[kFinBatch], ys[kFinBatch];
+        bool ok[kFinBatch];
+#pragma unroll
+        for (int k = 0; k < kFinBatch; ++k) {
+            const int e = e0 + k * 256;
+            const int rho = e / nV, gi = e - rho * nV;
+            const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
+            const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+            ok[k] = e < ncorner && c + dc < M && r >= rlo && r < rhi;
+            const int rr = ok[k] ? r : rlo, cc = ok[k] ? c : 0;
+            xs[k] = A[(int64_t)rr * in.lda + cc];
+            ys[k] = A[(int64_t)(rr + dr) * in.lda + cc + dc];
         }
-        V[cls * nVs + gi] = v;
+#pragma unroll
+        for (int k = 0; k < kFinBatch; ++k) {
+            const int e = e0 + k * 256;
+            if (e < ncorner)
+                V[(1 + e / nV) * nVs + e % nV] =
+                    ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
+                          : make_double2(0.0, 0.0);
+        }
     }
     __syncthreads();
 

@@ -58,12 +58,74 @@ __device__ __forceinline__ bool unique_lag(const Inst &in, int d1, int d2, int &
     return dc >= 0 && dc < in.Q && dr > -in.P && dr < in.P && (dc > 0 || dr >= 0);
 }
 
+// Widen 4 positions of the operands and return the 4 MFMAs per tile pair
+// that add them (issued by the caller after the next loads).
+template <int MT, int NT>
+__device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const float2 (&xn)[NT])
+{
+    double yr[MT], yi[MT], xr[NT], xi[NT], nxr[NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        yr[m] = (double)an[m].x;
+        yi[m] = (double)an[m].y;
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        xr[n] = (double)xn[n].x;
+        xi[n] = (double)xn[n].y;
+        nxr[n] = (double)(-xn[n].x);
+    }
+    return [=](v4d (&acc)[MT * NT][2]) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[m * NT + n][0] = mfma64(yr[m], xr[n], acc[m * NT + n][0]);
+                acc[m * NT + n][1] = mfma64(yr[m], xi[n], acc[m * NT + n][1]);
+            }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[m * NT + n][0] = mfma64(yi[m], xi[n], acc[m * NT + n][0]);
+                acc[m * NT + n][1] = mfma64(yi[m], nxr[n], acc[m * NT + n][1]);
+            }
+    };
+}
+
+// Run k-groups [k_a, k_b): the next k-group's loads are issued before this
+// one's products, so they overlap (the last iteration reloads its own
+// k-group: harmless); the scheduling barriers keep the compiler from moving
+// the loads back behind the conversions.
+template <int MT, int NT, class Load>
+__device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], float2 (&an)[MT],
+                                            float2 (&xn)[NT], Load load)
+{
+    load(k_a);
+    for (int kg = k_a; kg < k_b; ++kg) {
+        auto mf = kgroup_products<MT, NT>(an, xn);
+        __builtin_amdgcn_sched_barrier(0);
+        load(min(kg + 1, k_b - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mf(acc);
+    }
+}
+
 // One workgroup's job.  MT x NT tiles of 16 x 16 lags: rows d1 = d1lo + 16m + i,
 // columns d2 = d2lo + 16n + j.
+//
+// The first operand (16 lines by 4 positions per tile) is read with plain
+// loads: a wave-uniform base plus loop-invariant lane offsets, no vector
+// arithmetic.  They stay inside A because orientation 0 ends every line's
+// k-groups at the row's last column (the planner's k0), and orientation 1
+// clamps its positions in the one k-group that can pass row N-1.  The
+// line's own values (the second operand), zeroed outside [pos_lo, pos_hi),
+// are staged per wave in LDS, kMXCap of them at a time, and read from there.
 template <int MT, int NT, int OR>
 __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
 {
     constexpr int T = MT * NT;
+    constexpr int span = 16 * NT - 1;      // lane lags d2 in [d2lo, d2lo + span]
     const int lane = threadIdx.x & 63;
     // the wave index is uniform across the wave: keep it in a scalar register
     // so that branches on it (idle lines, the reduction tree) stay uniform
@@ -77,10 +139,15 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     const int npos = OR ? in.N : in.M;
     const int d1lo = OR ? 0 : -(in.P - 1);
     const int d2lo = OR ? -(in.P - 1) : 0;
+    // k-groups whose 4 positions all lie inside A
+    const int kin = (npos - 4 - job.k0) / 4 + 1;
 
     v4d acc[T][2];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t][0] = acc[t][1] = (v4d){0.0, 0.0, 0.0, 0.0};
+    float2 an[MT], xn[NT];
+    float2 *xb = reinterpret_cast<float2 *>(red) + wave * kMXCap;
+    const int chunk = (kMXCap - span) / 4;   // k-groups per staged chunk
 
     for (int bl = job.b0; bl <= job.b1; ++bl) {
         const int kga = bl == job.b0 ? job.kg0 : 0;
@@ -91,68 +158,59 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
         // Operand lines of this lane.  A line outside A only meets lags whose
         // sums the finalize never reads (or padding lags); its index is
         // clamped so that every load stays inside A.
+        int q[MT];
         uint32_t aoff[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            const int q = min(max(line + d1lo + 16 * m + i16, 0), nlines - 1);
-            aoff[m] = (uint32_t)q * ls;
+            q[m] = min(max(line + d1lo + 16 * m + i16, 0), nlines - 1);
+            aoff[m] = (uint32_t)q[m] * ls + (uint32_t)kq * ps;
         }
         const uint32_t xline = (uint32_t)line * ls;
-        int xlag[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) xlag[n] = d2lo + 16 * n + i16;
 
-        // Loads of one k-group: unconditional, from clamped (in-bounds)
-        // indices; x values outside the position range are zeroed after.
-        float2 an[MT], xn[NT];
-        bool xok[NT];
-        auto load = [&](int kg) {
-            const int pos = job.k0 + 4 * kg + kq;
-            const uint32_t pc = (uint32_t)min(pos, npos - 1) * ps;
+        for (int kc = kga; kc < kgb; kc += chunk) {
+            const int kce = min(kgb, kc + chunk);
+            const int xbase = job.k0 + 4 * kc - (d2lo + span);   // position of xb[0]
+            const int len = 4 * (kce - kc) + span;
+            // The previous chunk's reads were issued before these writes, and a
+            // wave's LDS operations run in order.  The loads go out 8 at a time
+            // before any is stored, so their latencies overlap.
+            for (int i0 = lane; i0 < len; i0 += 8 * 64) {
+                float2 v[8];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) an[m] = A[aoff[m] + pc];
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int xp = pos - xlag[n];
-                xok[n] = xp >= job.pos_lo && xp < job.pos_hi;
-                xn[n] = A[xline + (uint32_t)min(max(xp, 0), npos - 1) * ps];
-            }
-        };
-        load(kga);
-        for (int kg = kga; kg < kgb; ++kg) {
-            double yr[MT], yi[MT], xr[NT], xi[NT], nxr[NT];
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                yr[m] = (double)an[m].x;
-                yi[m] = (double)an[m].y;
-            }
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                xr[n] = xok[n] ? (double)xn[n].x : 0.0;
-                xi[n] = xok[n] ? (double)xn[n].y : 0.0;
-                nxr[n] = -xr[n];
-            }
-            // next k-group's loads overlap this one's products (the last
-            // iteration reloads its own k-group: harmless, branch-free); the
-            // scheduling barriers keep the compiler from moving the loads
-            // back behind the conversions above
-            __builtin_amdgcn_sched_barrier(0);
-            load(min(kg + 1, kgb - 1));
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    acc[m * NT + n][0] = mfma64(yr[m], xr[n], acc[m * NT + n][0]);
-                    acc[m * NT + n][1] = mfma64(yr[m], xi[n], acc[m * NT + n][1]);
+                for (int u = 0; u < 8; ++u) {
+                    const int p = xbase + i0 + 64 * u;
+                    const bool ok = p >= job.pos_lo && p < job.pos_hi;
+                    v[u] = A[xline + (uint32_t)(ok ? p : job.pos_lo) * ps];
+                    if (!ok) v[u] = make_float2(0.f, 0.f);
                 }
 #pragma unroll
-            for (int m = 0; m < MT; ++m)
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + 64 * u < len) xb[i0 + 64 * u] = v[u];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // lane (kq, j) of tile n reads position k0 + 4 kg + kq - (d2lo + 16 n + j)
+            const float2 *xl = xb + (kq - i16 + span);
+            auto load = [&](int kg, const uint32_t(&off)[MT]) {
+                const gfloat2 *Ak = A + (uint32_t)(job.k0 + 4 * kg) * ps;
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    acc[m * NT + n][0] = mfma64(yi[m], xi[n], acc[m * NT + n][0]);
-                    acc[m * NT + n][1] = mfma64(yi[m], nxr[n], acc[m * NT + n][1]);
-                }
+                for (int m = 0; m < MT; ++m) an[m] = Ak[off[m]];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) xn[n] = xl[4 * (kg - kc) - 16 * n];
+            };
+            const int kplain = min(kce, kin);
+            run_kgroups<MT, NT>(kc, kplain, acc, an, xn, [&](int kg) { load(kg, aoff); });
+            if (kplain < kce) {
+                // the last k-group of a line can pass A's last position: clamp
+                // it (at most one k-group; orientation 0 never gets here)
+                const int pos = job.k0 + 4 * kplain + kq;
+                uint32_t off[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    off[m] = (uint32_t)q[m] * ls + (uint32_t)(min(pos, npos - 1) - (job.k0 + 4 * kplain)) * ps;
+                run_kgroups<MT, NT>(kplain, kce, acc, an, xn, [&](int kg) { load(kg, off); });
+            }
         }
     }
 
@@ -186,6 +244,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     // and slot 0 adds slot 1 -- and wave 0 writes one partial row.  The
     // registers are only read here, never updated.
     constexpr int V = T * 8;   // doubles per lane
+    __syncthreads();   // the LDS held the staged lines until now
     auto at = [&](int slot, int t, int c, int r) -> double & {
         return red[((slot * V) + (t * 2 + c) * 4 + r) * 64 + lane];
     };
@@ -230,7 +289,7 @@ __global__ void __launch_bounds__(kMThreads, 2) rec_mfma(MfmaArgs ma)
     int b = blockIdx.x;
     if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
     const MJob job = ma.jobs[b];
-    const Inst in = ma.use_inline ? ma.inst_inline : ma.insts[job.inst];
+    const Inst &in = ma.inst;
     if (job.orient == 0) mfma_job<MT, NT, 0>(job, in, red);
     else mfma_job<NT, MT, 1>(job, in, red);
 }

@@ -355,7 +355,10 @@ def test_mfma_plan_ownership(shape, n_cu):
         o, kind, out, line0 = int(j[1]), int(j[2]), int(j[3]), int(j[4])
         assert j[10] == nkg[o]
         assert (j[11], j[12]) == ((info["Cm0"], info["Cm1"]) if o == 0 else (info["Rm0"], info["Rm1"]))
-        assert j[13] == (info["Cm0"] if o == 0 else info["Rm0"] - (P - 1))
+        # orientation 0 ends at A's last column (its first operand is read
+        # unchecked); orientation 1 starts at row 0
+        assert j[13] == (info["Cm1"] + Q - 1 - 4 * nkg[0] if o == 0 else info["Rm0"] - (P - 1))
+        assert j[13] >= 0 and j[13] + 4 * j[10] <= (M if o == 0 else N + 3)
         if kind == 0:
             assert o == 0 and (j[4], j[5]) == (info["Rm0"], info["Rm1"])
             bulk_outs.append(out)
