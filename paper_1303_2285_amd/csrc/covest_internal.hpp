@@ -26,6 +26,7 @@ namespace covest {
 
 constexpr int kWaves = 4;          // waves per workgroup of the main kernel
 constexpr int kThreads = 64 * kWaves;
+constexpr int kFinMaxRows = 160;   // individual rows the table finalize handles (n_ir)
 
 // A set of lanes of one wave slot: lane li has
 //   d1 = d1lo + li / nch,   d2 chunk start = ch0 + (li % nch) * W

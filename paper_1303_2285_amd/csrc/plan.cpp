@@ -95,7 +95,7 @@ static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
         }
     }
     const size_t table = (size_t)(1 + sp.n_ir) * (sp.n_ic | 1) * 16;
-    sp.fin_table = table <= kFinTableMax;
+    sp.fin_table = table <= kFinTableMax && sp.n_ir <= kFinMaxRows;
     sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
 
     sp.ws_bytes = (size_t)16 * sp.lag_stride *

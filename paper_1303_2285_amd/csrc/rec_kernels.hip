@@ -410,6 +410,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 {
     extern __shared__ double2 V[];
     __shared__ double2 red[256];
+    __shared__ double2 zrs[kFinMaxRows];   // row-strip sums of the individual rows
     const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
     const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
     const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
@@ -432,30 +433,15 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     const int nVs = nV | 1;   // odd row stride: no LDS bank conflicts across rows
     const int ncls = 1 + in.n_ir;
 
-    // Middle sum: fixed-order tree over the bulk partials.
-    double2 z = make_double2(0.0, 0.0);
-    for (int j = it.bulk0 + tid; j < it.bulk1; j += 256) z = cadd(z, partial[j * ls2 + lag]);
-    red[tid] = z;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = cadd(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    const double2 zm = red[0];
-
-    // Phase A: the table of individual-column terms of every row class.  The
-    // column-strip sums (class 0) come first; then the corner products, whose
-    // loads are issued kFinBatch at a time before any is used, so that their
-    // latencies overlap.
-    for (int gi = tid; gi < nV; gi += 256) {
-        const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
-        V[gi] = (has_mr && c + dc < M) ? ZC(gi) : make_double2(0.0, 0.0);
-    }
-    constexpr int kFinBatch = 8;
+    // Every global load of the item goes out before any result is used: the
+    // lag's bulk partials (two per thread, more in a loop if there are
+    // more), its column- and row-strip sums and the first kFinBatch corner
+    // products of each thread; so the item waits for about one load latency.
+    constexpr int kFinBatch = 16;
     const int ncorner = (ncls - 1) * nV;
-    for (int e0 = tid; e0 < ncorner; e0 += kFinBatch * 256) {
-        float2 xs[kFinBatch], ys[kFinBatch];
-        bool ok[kFinBatch];
+    float2 xs[kFinBatch], ys[kFinBatch];
+    bool ok[kFinBatch];
+    auto corner_loads = [&](int e0) {
 #pragma unroll
         for (int k = 0; k < kFinBatch; ++k) {
             const int e = e0 + k * 256;
@@ -467,6 +453,8 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
             xs[k] = A[(int64_t)rr * in.lda + cc];
             ys[k] = A[(int64_t)(rr + dr) * in.lda + cc + dc];
         }
+    };
+    auto corner_store = [&](int e0) {
 #pragma unroll
         for (int k = 0; k < kFinBatch; ++k) {
             const int e = e0 + k * 256;
@@ -475,6 +463,38 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
                     ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
                           : make_double2(0.0, 0.0);
         }
+    };
+    const int j0 = it.bulk0 + tid, j1 = j0 + 256;
+    const double2 p0 = j0 < it.bulk1 ? partial[j0 * ls2 + lag] : make_double2(0.0, 0.0);
+    const double2 p1 = j1 < it.bulk1 ? partial[j1 * ls2 + lag] : make_double2(0.0, 0.0);
+    const int cz = tid < Cm0 ? tid : Cm1 + (tid - Cm0);
+    const bool zc_ok = tid < nV && has_mr && cz + dc < M;
+    const double2 zc_v = zc_ok ? ZC(tid) : make_double2(0.0, 0.0);
+    for (int i = tid; i < in.n_ir; i += 256) zrs[i] = has_mc ? ZR(i) : make_double2(0.0, 0.0);
+    corner_loads(tid);
+
+    // Middle sum: fixed-order tree over the bulk partials.
+    double2 z = cadd(make_double2(0.0, 0.0), p0);
+    if (j1 < it.bulk1) z = cadd(z, p1);
+    for (int j = j1 + 256; j < it.bulk1; j += 256) z = cadd(z, partial[j * ls2 + lag]);
+    red[tid] = z;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = cadd(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const double2 zm = red[0];
+
+    // Phase A: the table of individual-column terms of every row class: the
+    // column-strip sums (class 0), then the corner products.
+    for (int gi = tid; gi < nV; gi += 256) {
+        const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
+        V[gi] = gi == tid ? zc_v : ((has_mr && c + dc < M) ? ZC(gi) : make_double2(0.0, 0.0));
+    }
+    corner_store(tid);
+    for (int e0 = tid + kFinBatch * 256; e0 < ncorner; e0 += kFinBatch * 256) {
+        corner_loads(e0);
+        corner_store(e0);
     }
     __syncthreads();
 
@@ -487,7 +507,9 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     const int nchunk_b = (nc + kFinChunk - 1) / kFinChunk;
     const int cls_per = 256 / nchunk_b;   // whole classes per pass: a class is never split
     for (int cbase = 0; cbase < ncls; cbase += cls_per) {
-        const int cls = cbase + tid / nchunk_b, ch = tid % nchunk_b;
+        // neighbouring threads take neighbouring classes: rows nVs apart,
+        // which fall in different LDS banks
+        const int cls = cbase + tid % cls_per, ch = tid / cls_per;
         double2 res[kFinChunk];
         bool live = tid < cls_per * nchunk_b && cls < ncls;
         if (live && cls > 0) {
@@ -500,7 +522,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
             const double2 *row = V + cls * nVs;
             double2 s;
             if (cls == 0) s = has_mr ? zm : make_double2(0.0, 0.0);
-            else s = has_mc ? ZR(cls - 1) : make_double2(0.0, 0.0);
+            else s = zrs[cls - 1];
             // columns [b0, b0 + Kc) of the individual set: left part, right part
             for (int gi = b0; gi < min(Cm0, b0 + Kc); ++gi) s = cadd(s, row[gi]);
             for (int c = max(Cm1, b0); c < b0 + Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);

@@ -98,14 +98,14 @@ __device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const fl
 // k-group: harmless); the scheduling barriers keep the compiler from moving
 // the loads back behind the conversions.
 template <int MT, int NT, class Load>
-__device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], float2 (&an)[MT],
-                                            float2 (&xn)[NT], Load load)
+__device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], Load load)
 {
-    load(k_a);
+    float2 an[MT], xn[NT];
+    load(k_a, an, xn);
     for (int kg = k_a; kg < k_b; ++kg) {
         auto mf = kgroup_products<MT, NT>(an, xn);
         __builtin_amdgcn_sched_barrier(0);
-        load(min(kg + 1, k_b - 1));
+        load(min(kg + 1, k_b - 1), an, xn);
         __builtin_amdgcn_sched_barrier(0);
         mf(acc);
     }
@@ -145,7 +145,6 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     v4d acc[T][2];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t][0] = acc[t][1] = (v4d){0.0, 0.0, 0.0, 0.0};
-    float2 an[MT], xn[NT];
     float2 *xb = reinterpret_cast<float2 *>(red) + wave * kMXCap;
     const int chunk = (kMXCap - span) / 4;   // k-groups per staged chunk
 
@@ -192,7 +191,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // lane (kq, j) of tile n reads position k0 + 4 kg + kq - (d2lo + 16 n + j)
             const float2 *xl = xb + (kq - i16 + span);
-            auto load = [&](int kg, const uint32_t(&off)[MT]) {
+            auto load = [&](int kg, const uint32_t(&off)[MT], float2(&an)[MT], float2(&xn)[NT]) {
                 const gfloat2 *Ak = A + (uint32_t)(job.k0 + 4 * kg) * ps;
 #pragma unroll
                 for (int m = 0; m < MT; ++m) an[m] = Ak[off[m]];
@@ -200,7 +199,8 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
                 for (int n = 0; n < NT; ++n) xn[n] = xl[4 * (kg - kc) - 16 * n];
             };
             const int kplain = min(kce, kin);
-            run_kgroups<MT, NT>(kc, kplain, acc, an, xn, [&](int kg) { load(kg, aoff); });
+            run_kgroups<MT, NT>(kc, kplain, acc,
+                                [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, aoff, an, xn); });
             if (kplain < kce) {
                 // the last k-group of a line can pass A's last position: clamp
                 // it (at most one k-group; orientation 0 never gets here)
@@ -209,7 +209,8 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     off[m] = (uint32_t)q[m] * ls + (uint32_t)(min(pos, npos - 1) - (job.k0 + 4 * kplain)) * ps;
-                run_kgroups<MT, NT>(kplain, kce, acc, an, xn, [&](int kg) { load(kg, off); });
+                run_kgroups<MT, NT>(kplain, kce, acc,
+                                    [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, off, an, xn); });
             }
         }
     }
