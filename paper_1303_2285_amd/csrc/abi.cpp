@@ -258,7 +258,6 @@ Inst make_inst(const ShapePlan &sp, const void *A, int64_t lda, void *R, int64_t
     in.partial = base;
     in.zr = base + (size_t)2 * sp.lag_stride * sp.n_bulk;
     in.zc = in.zr + (size_t)2 * sp.lag_stride * sp.n_ir * sp.zpieces;
-    in.a64 = sp.engine == 2 ? static_cast<char *>(ws) + sp.a64_offset : nullptr;
     in.out_fp64 = o.prec == COVEST_PREC_FP64 ? 1 : 0;
     in.fill_full = o.fill == COVEST_FILL_FULL ? 1 : 0;
     in.normalize = o.normalize ? 1 : 0;
@@ -287,11 +286,10 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     if (engine == 0)
         return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N >= 2P-1, M >= 2Q-1 and a lag "
                                             "block of at most 8 tiles of 16 x 16 with little padding");
-    // the matrix-core kernel addresses its complex128 copy of A with 32-bit
-    // byte offsets
-    if (engine == 2 && (int64_t)N * M * 16 >= ((int64_t)1 << 32)) {
+    // the matrix-core kernel addresses A with 32-bit element offsets
+    if (engine == 2 && (int64_t)N * lda + M >= ((int64_t)1 << 31)) {
         if (o.engine == COVEST_ENGINE_MATRIX)
-            return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs 16 N M < 2^32");
+            return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N * lda < 2^31");
         engine = 1;
     }
     DevPlan *dp = nullptr;
@@ -307,7 +305,6 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
         ma.n_jobs = (int)sp.mjobs.size();
         ma.xcd_remap = dp->xcd_remap;
         ma.inst = in;
-        HIP_TRY(timed("widen_a", stream, [&] { return launch_widen_a(A, lda, N, M, in.a64, stream); }));
         HIP_TRY(timed("rec_mfma", stream, [&] {
             return launch_rec_mfma(ma, sp.mt, sp.nt, (int)sp.mjobs.size(), sp.lds_main, stream);
         }));

@@ -83,7 +83,6 @@ struct Inst {
     double *partial;          // [n_bulk_jobs][lag_stride] complex FP64 (as 2 doubles)
     double *zr;               // [n_ir][lag_stride]
     double *zc;               // [n_ic][lag_stride]
-    void *a64;                // matrix-core engine: A widened to complex128, row stride M
     int out_fp64;             // R element: 1 complex128, 0 complex64
     int fill_full;            // 1: write the conjugate mirror too
     int normalize;            // 1: divide by K
@@ -122,7 +121,7 @@ struct MainArgs {
 // lines at the same positions.
 constexpr int kMWaves = 8;
 constexpr int kMThreads = 64 * kMWaves;
-constexpr int kMXCap = 1024;   // line values staged per line (complex128) by the matrix-core pass
+constexpr int kMXCap = 2048;   // first factors staged per wave (float2), orientation 0
 
 enum MJobKind : int { kMBulk = 0, kMStrip = 1 };
 

@@ -17,7 +17,5 @@ hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes
 
 // Matrix-core main pass (rec_mfma.hip): mt x nt tiles of the orientation-0 lag block.
 hipError_t launch_rec_mfma(const MfmaArgs &ma, int mt, int nt, int n_blocks, size_t lds, hipStream_t stream);
-// A (complex64, row stride lda) widened to complex128 with row stride M.
-hipError_t launch_widen_a(const void *A, int64_t lda, int N, int M, void *a64, hipStream_t stream);
 
 }  // namespace covest

@@ -413,14 +413,11 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
         sp.job_cost.push_back((double)(j.kg1 - j.kg0));
     }
     sp.lds_main = std::max((size_t)4 * 8 * sp.mt * sp.nt * 64 * sizeof(double),
-                           (size_t)kMWaves * kMXCap * 16);
+                           (size_t)kMWaves * kMXCap * 8);
     finish_plan(sp, [&](int, int, FinItem &it) {
         it.bulk0 = 0;
         it.bulk1 = sp.n_bulk;
     });
-    // A widened to complex128 follows the sums
-    sp.a64_offset = (sp.ws_bytes + 255) / 256 * 256;
-    sp.ws_bytes = sp.a64_offset + (size_t)16 * N * M;
     return sp;
 }
 

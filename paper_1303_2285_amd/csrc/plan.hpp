@@ -42,7 +42,6 @@ struct ShapePlan {
     // matrix-core engine only
     int mt = 0, nt = 0;                  // 16 x 16 tiles of the orientation-0 lag block (d1 = dr, d2 = dc)
     int zpieces = 1;                     // pieces per strip line
-    size_t a64_offset = 0;               // workspace offset of A widened to complex128
     std::vector<MJob> mjobs;
 };
 

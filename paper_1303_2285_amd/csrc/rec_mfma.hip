@@ -20,17 +20,13 @@
 // Complex arithmetic: the four real parts of a complex multiply-add are four
 // real products over the same 4 positions,
 //     Re T += yr*xr + yi*xi,      Im T += yr*xi + yi*(-xr),
-// i.e. four MFMAs per 16 x 16 tile pair per k-group (the minus sign is the
-// instruction's negate modifier on the second operand).  A prepass widens A
-// once to complex128 (widen_a), so the loop reads FP64 operands directly;
-// products of two floats are exact in FP64, sums accumulate in FP64 inside
-// the matrix core.
+// i.e. four MFMAs per 16 x 16 tile pair per k-group.  Operands come straight
+// from A (complex64) and are widened to FP64 in registers; products of two
+// floats are exact in FP64, sums accumulate in FP64 inside the matrix core.
 //
 // MFMA lane layout of v_mfma_f64_16x16x4 (gfx950): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; result register r of lane l holds D[l/16 + 4r][l%16].
 #include <hip/hip_runtime.h>
-
-#include <algorithm>
 
 #include "covest_internal.hpp"
 #include "device_util.hpp"
@@ -42,51 +38,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // flat_load, which also waits on the LDS counter).  The host pass of the
 // compiler has no address spaces.
 #if defined(__HIP_DEVICE_COMPILE__)
-typedef __attribute__((address_space(1))) const double2 gdouble2;
-typedef __attribute__((address_space(1))) const char gchar;
+typedef __attribute__((address_space(1))) const float2 gfloat2;
 #else
-typedef const double2 gdouble2;
-typedef const char gchar;
+typedef const float2 gfloat2;
 #endif
 
-// *(base + byte offset): a 32-bit unsigned offset from a wave-uniform base
-// compiles to the scalar-base form of global_load (no per-lane address math).
-__device__ __forceinline__ double2 ld_at(const gchar *base, uint32_t off)
-{
-    return *reinterpret_cast<const gdouble2 *>(base + off);
-}
-
-// c + a * b, and c - a * b (negate modifier on the second operand)
 __device__ __forceinline__ v4d mfma64(double a, double b, v4d c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4d mfma64_nb(double a, double b, v4d c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 2);
-}
-
-// A (complex64, row stride lda) -> a64 (complex128, row stride M).  Block b
-// widens 1024 consecutive values of one row: row b / cpr, columns from
-// (b % cpr) * 1024, cpr = ceil(M / 1024); each thread takes 4.
-__global__ void __launch_bounds__(256) widen_a(const float2 *__restrict__ A, int64_t lda, int M, int cpr,
-                                               double2 *__restrict__ a64)
-{
-    const int r = blockIdx.x / cpr;
-    const int c0 = (blockIdx.x - r * cpr) * 1024;
-    const float2 *src = A + (int64_t)r * lda;
-    double2 *dst = a64 + (int64_t)r * M;
-    float2 v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int c = c0 + u * 256 + threadIdx.x;
-        v[u] = c < M ? src[c] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int c = c0 + u * 256 + threadIdx.x;
-        if (c < M) dst[c] = make_double2((double)v[u].x, (double)v[u].y);
-    }
 }
 
 // Lag (d1, d2) of orientation OR -> (dr, dc); true if it is a unique
@@ -99,93 +58,95 @@ __device__ __forceinline__ bool unique_lag(const Inst &in, int d1, int d2, int &
     return dc >= 0 && dc < in.Q && dr > -in.P && dr < in.P && (dc > 0 || dr >= 0);
 }
 
-// The 4 MFMAs per tile pair that add one k-group (4 positions).
+// Widen 4 positions of the operands and return the 4 MFMAs per tile pair
+// that add them (issued by the caller after the next loads).
 template <int MT, int NT>
-__device__ __forceinline__ void kgroup_mfma(v4d (&acc)[MT * NT][2], const double2 (&an)[MT],
-                                            const double2 (&xn)[NT])
+__device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const float2 (&xn)[NT])
 {
+    double yr[MT], yi[MT], xr[NT], xi[NT], nxr[NT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m) {
+        yr[m] = (double)an[m].x;
+        yi[m] = (double)an[m].y;
+    }
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            acc[m * NT + n][0] = mfma64(an[m].x, xn[n].x, acc[m * NT + n][0]);
-            acc[m * NT + n][1] = mfma64(an[m].x, xn[n].y, acc[m * NT + n][1]);
-        }
+    for (int n = 0; n < NT; ++n) {
+        xr[n] = (double)xn[n].x;
+        xi[n] = (double)xn[n].y;
+        nxr[n] = (double)(-xn[n].x);
+    }
+    return [=](v4d (&acc)[MT * NT][2]) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            acc[m * NT + n][0] = mfma64(an[m].y, xn[n].y, acc[m * NT + n][0]);
-            acc[m * NT + n][1] = mfma64_nb(an[m].y, xn[n].x, acc[m * NT + n][1]);
-        }
+            for (int n = 0; n < NT; ++n) {
+                acc[m * NT + n][0] = mfma64(yr[m], xr[n], acc[m * NT + n][0]);
+                acc[m * NT + n][1] = mfma64(yr[m], xi[n], acc[m * NT + n][1]);
+            }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[m * NT + n][0] = mfma64(yi[m], xi[n], acc[m * NT + n][0]);
+                acc[m * NT + n][1] = mfma64(yi[m], nxr[n], acc[m * NT + n][1]);
+            }
+    };
 }
 
-// Run k-groups [k_a, k_b) from two register sets: each k-group's products
-// are issued after the next k-group's loads, which go into the other set, so
-// loads and products overlap without copies.  The scheduling barriers keep
-// the compiler from moving the loads behind the products.
+// Run k-groups [k_a, k_b): the next k-group's loads are issued before this
+// one's products, so they overlap (the last iteration reloads its own
+// k-group: harmless); the scheduling barriers keep the compiler from moving
+// the loads back behind the conversions.
 template <int MT, int NT, class Load>
 __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], Load load)
 {
-    double2 a0[MT], x0[NT], a1[MT], x1[NT];
-    load(k_a, a0, x0);
-    for (int kg = k_a; kg < k_b; kg += 2) {
+    float2 an[MT], xn[NT];
+    load(k_a, an, xn);
+    for (int kg = k_a; kg < k_b; ++kg) {
+        auto mf = kgroup_products<MT, NT>(an, xn);
         __builtin_amdgcn_sched_barrier(0);
-        load(min(kg + 1, k_b - 1), a1, x1);
+        load(min(kg + 1, k_b - 1), an, xn);
         __builtin_amdgcn_sched_barrier(0);
-        kgroup_mfma<MT, NT>(acc, a0, x0);
-        if (kg + 1 < k_b) {
-            __builtin_amdgcn_sched_barrier(0);
-            load(min(kg + 2, k_b - 1), a0, x0);
-            __builtin_amdgcn_sched_barrier(0);
-            kgroup_mfma<MT, NT>(acc, a1, x1);
-        }
+        mf(acc);
     }
 }
 
-// One workgroup's job.  The lag block of the orientation has 16 x 16 tiles;
-// H waves share a line, wave part h holding the MT x NT tiles of the h-th part
-// of the dr range: for orientation 0 (d1 = dr) the tile rows [h MT, (h+1) MT),
-// for orientation 1 (d2 = dr) the tile columns [h NT, (h+1) NT).  Rows
-// d1 = d1lo + 16m + i, columns d2 = d2lo + 16n + j.
+// One workgroup's job.  MT x NT tiles of 16 x 16 lags: rows d1 = d1lo + 16m + i,
+// columns d2 = d2lo + 16n + j.
 //
 // The first operand (16 lines by 4 positions per tile) is read with plain
-// loads from the widened copy: a wave-uniform base plus loop-invariant lane
-// offsets, no vector arithmetic.  They stay inside A because orientation 0
-// ends every line's k-groups at the row's last column (the planner's k0), and
-// orientation 1 clamps its positions in the one k-group that can pass row
-// N-1.  The line's own values (the second operand), zeroed outside
-// [pos_lo, pos_hi), are staged per wave in LDS, kMXCap / H of them at a
-// time, and read from there.
-template <int MT, int NT, int OR, int H>
+// loads: a wave-uniform base plus loop-invariant lane offsets, no vector
+// arithmetic.  They stay inside A because orientation 0 ends every line's
+// k-groups at the row's last column (the planner's k0), and orientation 1
+// clamps its positions in the one k-group that can pass row N-1.  The
+// line's own values (the second operand), zeroed outside [pos_lo, pos_hi),
+// are staged per wave in LDS, kMXCap of them at a time, and read from there.
+template <int MT, int NT, int OR>
 __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
 {
     constexpr int T = MT * NT;
     constexpr int span = 16 * NT - 1;      // lane lags d2 in [d2lo, d2lo + span]
-    constexpr int cap = kMXCap / H;        // staged values per wave
     const int lane = threadIdx.x & 63;
     // the wave index is uniform across the wave: keep it in a scalar register
     // so that branches on it (idle lines, the reduction tree) stay uniform
-    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wave = wave_id / H, part = wave_id % H;   // line of the block, part of the lag block
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, kq = lane >> 4;
-    // byte offsets inside the widened copy fit in 32 bits (the engine needs
-    // 16 N M < 2^32)
-    const gdouble2 *A = (const gdouble2 *)in.a64;   // row stride M
-    const uint32_t ls = OR ? 1u : (uint32_t)in.M;   // between lines
-    const uint32_t ps = OR ? (uint32_t)in.M : 1u;   // between positions along a line
+    const gfloat2 *A = (const gfloat2 *)in.A;
+    // element offsets fit in 32 bits (the planner checks N * lda < 2^31)
+    const uint32_t ls = OR ? 1u : (uint32_t)in.lda;   // between lines
+    const uint32_t ps = OR ? (uint32_t)in.lda : 1u;   // between positions along a line
     const int nlines = OR ? in.M : in.N;
     const int npos = OR ? in.N : in.M;
-    const int d1lo = OR ? 0 : -(in.P - 1) + 16 * MT * part;
-    const int d2lo = OR ? -(in.P - 1) + 16 * NT * part : 0;
+    const int d1lo = OR ? 0 : -(in.P - 1);
+    const int d2lo = OR ? -(in.P - 1) : 0;
     // k-groups whose 4 positions all lie inside A
     const int kin = (npos - 4 - job.k0) / 4 + 1;
 
     v4d acc[T][2];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t][0] = acc[t][1] = (v4d){0.0, 0.0, 0.0, 0.0};
-    double2 *xb = reinterpret_cast<double2 *>(red) + wave_id * cap;
-    const int chunk = (cap - span) / 4;   // k-groups per staged chunk
+    float2 *xb = reinterpret_cast<float2 *>(red) + wave * kMXCap;
+    const int chunk = (kMXCap - span) / 4;   // k-groups per staged chunk
 
     for (int bl = job.b0; bl <= job.b1; ++bl) {
         const int kga = bl == job.b0 ? job.kg0 : 0;
@@ -201,7 +162,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             q[m] = min(max(line + d1lo + 16 * m + i16, 0), nlines - 1);
-            aoff[m] = ((uint32_t)q[m] * ls + (uint32_t)kq * ps) * 16u;   // bytes
+            aoff[m] = (uint32_t)q[m] * ls + (uint32_t)kq * ps;
         }
         const uint32_t xline = (uint32_t)line * ls;
 
@@ -213,13 +174,13 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
             // wave's LDS operations run in order.  The loads go out 8 at a time
             // before any is stored, so their latencies overlap.
             for (int i0 = lane; i0 < len; i0 += 8 * 64) {
-                double2 v[8];
+                float2 v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int p = xbase + i0 + 64 * u;
                     const bool ok = p >= job.pos_lo && p < job.pos_hi;
                     v[u] = A[xline + (uint32_t)(ok ? p : job.pos_lo) * ps];
-                    if (!ok) v[u] = make_double2(0.0, 0.0);
+                    if (!ok) v[u] = make_float2(0.f, 0.f);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
@@ -229,17 +190,17 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // lane (kq, j) of tile n reads position k0 + 4 kg + kq - (d2lo + 16 n + j)
-            const double2 *xl = xb + (kq - i16 + span);
-            auto load = [&](int kg, const uint32_t(&off)[MT], double2(&an)[MT], double2(&xn)[NT]) {
-                const gchar *Ak = reinterpret_cast<const gchar *>(A) + (size_t)(job.k0 + 4 * kg) * ps * 16;
+            const float2 *xl = xb + (kq - i16 + span);
+            auto load = [&](int kg, const uint32_t(&off)[MT], float2(&an)[MT], float2(&xn)[NT]) {
+                const gfloat2 *Ak = A + (uint32_t)(job.k0 + 4 * kg) * ps;
 #pragma unroll
-                for (int m = 0; m < MT; ++m) an[m] = ld_at(Ak, off[m]);
+                for (int m = 0; m < MT; ++m) an[m] = Ak[off[m]];
 #pragma unroll
                 for (int n = 0; n < NT; ++n) xn[n] = xl[4 * (kg - kc) - 16 * n];
             };
             const int kplain = min(kce, kin);
             run_kgroups<MT, NT>(kc, kplain, acc,
-                                [&](int kg, double2(&an)[MT], double2(&xn)[NT]) { load(kg, aoff, an, xn); });
+                                [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, aoff, an, xn); });
             if (kplain < kce) {
                 // the last k-group of a line can pass A's last position: clamp
                 // it (at most one k-group; orientation 0 never gets here)
@@ -247,9 +208,9 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
                 uint32_t off[MT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
-                    off[m] = ((uint32_t)q[m] * ls + (uint32_t)(min(pos, npos - 1) - (job.k0 + 4 * kplain)) * ps) * 16u;
+                    off[m] = (uint32_t)q[m] * ls + (uint32_t)(min(pos, npos - 1) - (job.k0 + 4 * kplain)) * ps;
                 run_kgroups<MT, NT>(kplain, kce, acc,
-                                    [&](int kg, double2(&an)[MT], double2(&xn)[NT]) { load(kg, off, an, xn); });
+                                    [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, off, an, xn); });
             }
         }
     }
@@ -279,15 +240,14 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
         return;
     }
 
-    // Bulk: for each part of the lag block, the sums of the block's 8 lines
-    // are added in a fixed order through LDS -- slot s (s < 4) gets line s+4
-    // plus line s, slot s (s < 2) then adds slot s+2, and slot 0 adds slot 1 --
-    // and line 0's wave writes the part into one partial row.  The registers
-    // are only read here, never updated.
+    // Bulk: the waves' sums are added in a fixed order through LDS -- slot s
+    // (s < 4) gets wave s+4 plus wave s, slot s (s < 2) then adds slot s+2,
+    // and slot 0 adds slot 1 -- and wave 0 writes one partial row.  The
+    // registers are only read here, never updated.
     constexpr int V = T * 8;   // doubles per lane
     __syncthreads();   // the LDS held the staged lines until now
     auto at = [&](int slot, int t, int c, int r) -> double & {
-        return red[(((part * 4 + slot) * V) + (t * 2 + c) * 4 + r) * 64 + lane];
+        return red[((slot * V) + (t * 2 + c) * 4 + r) * 64 + lane];
     };
     if (wave >= 4) {
 #pragma unroll
@@ -321,52 +281,39 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
                   [&](int t, int c, int r) { return at(0, t, c, r) + at(1, t, c, r); });
 }
 
-// One workgroup per job: kMWaves lines, H waves per line.  (MT, NT) is the
-// tile shape one wave holds for orientation 0 (rows dr, columns dc);
-// orientation-1 jobs use the transposed shape (rows dc, columns dr).
-template <int MT, int NT, int H>
-__global__ void __launch_bounds__(kMThreads * H) rec_mfma(MfmaArgs ma)
+// One workgroup per job; orientation-1 jobs use the transposed tile shape
+// (their d1 runs over Q column lags, d2 over 2P-1 row lags).
+template <int MT, int NT>
+__global__ void __launch_bounds__(kMThreads, 2) rec_mfma(MfmaArgs ma)
 {
     extern __shared__ double red[];
     int b = blockIdx.x;
     if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
     const MJob job = ma.jobs[b];
     const Inst &in = ma.inst;
-    if (job.orient == 0) mfma_job<MT, NT, 0, H>(job, in, red);
-    else mfma_job<NT, MT, 1, H>(job, in, red);
+    if (job.orient == 0) mfma_job<MT, NT, 0>(job, in, red);
+    else mfma_job<NT, MT, 1>(job, in, red);
 }
 
-template <int MT, int NT, int H>
-static hipError_t launch_tiles(const MfmaArgs &ma, int n_blocks, size_t lds, hipStream_t stream)
+template <int MT, int NT>
+static hipError_t launch_mt_nt(const MfmaArgs &ma, int n_blocks, size_t lds, hipStream_t stream)
 {
-    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_mfma<MT, NT, H>),
+    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_mfma<MT, NT>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((rec_mfma<MT, NT, H>), dim3(n_blocks), dim3(kMThreads * H), lds, stream, ma);
+    hipLaunchKernelGGL((rec_mfma<MT, NT>), dim3(n_blocks), dim3(kMThreads), lds, stream, ma);
     return hipGetLastError();
 }
 
-hipError_t launch_widen_a(const void *A, int64_t lda, int N, int M, void *a64, hipStream_t stream)
-{
-    const int cpr = (M + 1023) / 1024;
-    hipLaunchKernelGGL(widen_a, dim3((unsigned)((int64_t)N * cpr)), dim3(256), 0, stream,
-                       static_cast<const float2 *>(A), lda, M, cpr, static_cast<double2 *>(a64));
-    return hipGetLastError();
-}
-
-// mt x nt: the whole orientation-0 lag block.  An even mt is split over two
-// waves per line (half the accumulators each, twice the waves per SIMD) where
-// the halves fit in 128 registers.
 hipError_t launch_rec_mfma(const MfmaArgs &ma, int mt, int nt, int n_blocks, size_t lds, hipStream_t stream)
 {
-#define COVEST_TILES(a, b, h) \
-    if (mt == a * h && nt == b) return launch_tiles<a, b, h>(ma, n_blocks, lds, stream);
-    COVEST_TILES(1, 1, 2) COVEST_TILES(1, 2, 2) COVEST_TILES(1, 3, 2) COVEST_TILES(2, 1, 2)
-    COVEST_TILES(2, 2, 2) COVEST_TILES(3, 1, 2)
-    COVEST_TILES(1, 1, 1) COVEST_TILES(1, 2, 1) COVEST_TILES(1, 3, 1) COVEST_TILES(1, 4, 1)
-    COVEST_TILES(2, 4, 1) COVEST_TILES(3, 1, 1) COVEST_TILES(3, 2, 1) COVEST_TILES(5, 1, 1)
-    COVEST_TILES(7, 1, 1) COVEST_TILES(8, 1, 1)
-#undef COVEST_TILES
+#define COVEST_MT_NT(a, b) \
+    if (mt == a && nt == b) return launch_mt_nt<a, b>(ma, n_blocks, lds, stream);
+    COVEST_MT_NT(1, 1) COVEST_MT_NT(1, 2) COVEST_MT_NT(1, 3) COVEST_MT_NT(1, 4)
+    COVEST_MT_NT(2, 1) COVEST_MT_NT(2, 2) COVEST_MT_NT(2, 3) COVEST_MT_NT(2, 4)
+    COVEST_MT_NT(3, 1) COVEST_MT_NT(3, 2) COVEST_MT_NT(4, 1) COVEST_MT_NT(4, 2)
+    COVEST_MT_NT(5, 1) COVEST_MT_NT(6, 1) COVEST_MT_NT(7, 1) COVEST_MT_NT(8, 1)
+#undef COVEST_MT_NT
     return hipErrorInvalidValue;
 }
 
