@@ -15,7 +15,8 @@ import os
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcovest.so")
+# the in-tree build; COVEST_LIB names another build of the same library (e.g. to compare two)
+LIB_PATH = os.environ.get("COVEST_LIB") or os.path.join(HERE, "libcovest.so")
 
 OK = 0
 ERR_INVALID_ARG = -1
