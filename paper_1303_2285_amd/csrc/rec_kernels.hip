@@ -401,6 +401,23 @@ __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
     }
 }
 
+// s + t[lo·st] + t[(lo+1)·st] + ... + t[(hi−1)·st], added in index order.  The
+// LDS reads of each group of kChainGroup terms are issued together, so the
+// chain waits for one read latency per group instead of one per term.
+constexpr int kChainGroup = 8;
+__device__ __forceinline__ double2 lds_chain(double2 s, const double2 *t, int lo, int hi, int st)
+{
+    for (int g = lo; g < hi; g += kChainGroup) {
+        double2 v[kChainGroup];
+#pragma unroll
+        for (int k = 0; k < kChainGroup; ++k) v[k] = t[min(g + k, hi - 1) * st];
+#pragma unroll
+        for (int k = 0; k < kChainGroup; ++k)
+            if (g + k < hi) s = cadd(s, v[k]);
+    }
+    return s;
+}
+
 // Table variant of the finalize (256 threads, one unique combination): every
 // product the sliding needs is computed at once into an LDS table (rows:
 // the middle class and each individual row; columns: the individual columns),
@@ -524,8 +541,8 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
             if (cls == 0) s = has_mr ? zm : make_double2(0.0, 0.0);
             else s = zrs[cls - 1];
             // columns [b0, b0 + Kc) of the individual set: left part, right part
-            for (int gi = b0; gi < min(Cm0, b0 + Kc); ++gi) s = cadd(s, row[gi]);
-            for (int c = max(Cm1, b0); c < b0 + Kc; ++c) s = cadd(s, row[Cm0 + c - Cm1]);
+            s = lds_chain(s, row, b0, min(Cm0, b0 + Kc), 1);
+            s = lds_chain(s, row, Cm0 + max(Cm1, b0) - Cm1, Cm0 + b0 + Kc - Cm1, 1);
 #pragma unroll
             for (int k = 0; k < kFinChunk; ++k) {
                 const int b = b0 + k;
@@ -552,16 +569,27 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
         const int a0 = ch * kFinChunk, a1 = min(nr, a0 + kFinChunk);
         const int i0 = rlo + a0;
         double2 s = V[b];
-        for (int r = i0; r < min(Rm0, i0 + Kr); ++r) s = cadd(s, V[(1 + r) * nVs + b]);
-        for (int r = max(Rm1, i0); r < i0 + Kr; ++r) s = cadd(s, V[(1 + Rm0 + r - Rm1) * nVs + b]);
-        for (int a = a0; a < a1; ++a) {
-            const int i1 = rlo + a;
-            const int k1 = i1 + P * b;
-            const int k2 = (i1 + dr) + P * (b + dc);
-            store_r(in, k1, k2, s, dr == 0 && dc == 0);
-            if (a + 1 < a1) {
-                s = csub(s, V[(1 + i1) * nVs + b]);
-                s = cadd(s, V[(1 + Rm0 + i1 + Kr - Rm1) * nVs + b]);
+        s = lds_chain(s, V + nVs + b, i0, min(Rm0, i0 + Kr), nVs);
+        s = lds_chain(s, V + nVs + b, Rm0 + max(Rm1, i0) - Rm1, Rm0 + i0 + Kr - Rm1, nVs);
+        // the rows leaving and entering at each step, read up front (a step
+        // that does not slide reads entry b of class 0 instead, and drops it)
+        double2 vout[kFinChunk - 1], vin[kFinChunk - 1];
+#pragma unroll
+        for (int k = 0; k + 1 < kFinChunk; ++k) {
+            const int i1 = rlo + a0 + k;
+            const bool sl = a0 + k + 1 < a1;
+            vout[k] = V[sl ? (1 + i1) * nVs + b : b];
+            vin[k] = V[sl ? (1 + Rm0 + i1 + Kr - Rm1) * nVs + b : b];
+        }
+#pragma unroll
+        for (int k = 0; k < kFinChunk; ++k) {
+            const int a = a0 + k;
+            if (a < a1) {
+                const int i1 = rlo + a;
+                const int k1 = i1 + P * b;
+                const int k2 = (i1 + dr) + P * (b + dc);
+                store_r(in, k1, k2, s, dr == 0 && dc == 0);
+                if (k + 1 < kFinChunk && a + 1 < a1) s = cadd(csub(s, vout[k]), vin[k]);
             }
         }
     }
