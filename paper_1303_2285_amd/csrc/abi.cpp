@@ -442,7 +442,7 @@ int hankel_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void 
 // --------------------------------------------------------------- adjoint ----
 struct AdjGeom {
     int ir0, ir1, ic0, ic1, ndc, n_lags, interior_blocks;
-    int64_t n_frame;
+    int64_t frame_jobs;
     size_t lds_tables, lds_interior, ws_bytes;
 };
 
@@ -469,7 +469,11 @@ AdjGeom adj_geometry(int N, int M, int P, int Q)
         g.ic0 = g.ic1 = 0;
         g.interior_blocks = 0;
     }
-    g.n_frame = (int64_t)N * M - (int64_t)(g.ir1 - g.ir0) * (g.ic1 - g.ic0);
+    // frame jobs: border rows x interior-column lines, border columns x
+    // interior-row lines, border rows x border columns
+    const int64_t nbr = N - (g.ir1 - g.ir0), nbc = M - (g.ic1 - g.ic0);
+    g.frame_jobs = nbr * ((g.ic1 - g.ic0 + kAdjFL - 1) / kAdjFL) + nbc * ((g.ir1 - g.ir0 + kAdjFL - 1) / kAdjFL) +
+                   nbr * nbc;
     g.ws_bytes = (size_t)g.n_lags * (P + 1) * (Q + 1) * 16 + (size_t)g.n_lags * 16;
     return g;
 }
@@ -879,6 +883,9 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
     const AdjGeom g = adj_geometry((int)N, (int)M, (int)P, (int)Q);
     if (ws_bytes < g.ws_bytes || ws == nullptr)
         return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.ws_bytes, ws_bytes);
+    if (g.frame_jobs > INT32_MAX)
+        return fail(COVEST_ERR_UNSUPPORTED, "the adjoint's border needs %lld jobs, more than one launch holds",
+                    (long long)g.frame_jobs);
     AdjArgs aa{};
     aa.A = static_cast<const float2 *>(A);
     aa.lda = M;
@@ -897,12 +904,11 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
     aa.ic0 = g.ic0;
     aa.ic1 = g.ic1;
     aa.ndc = g.ndc;
-    aa.n_frame = g.n_frame;
     aa.tables = static_cast<double *>(ws);
     aa.hfull = aa.tables + (size_t)2 * g.n_lags * (P + 1) * (Q + 1);
     aa.normalize = o.normalize ? 1 : 0;
     HIP_TRY(timed("adjoint", stream, [&] {
-        return launch_adjoint(aa, g.n_lags, g.lds_tables, g.interior_blocks, g.lds_interior, g.n_frame, stream);
+        return launch_adjoint(aa, g.n_lags, g.lds_tables, g.interior_blocks, g.lds_interior, g.frame_jobs, stream);
     }));
     return finish_call(stream);
 }

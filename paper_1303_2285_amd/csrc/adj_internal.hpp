@@ -9,6 +9,8 @@ namespace covest {
 
 constexpr int kAdjTR = 16;   // interior outputs per workgroup: rows
 constexpr int kAdjTC = 64;   // interior outputs per workgroup: columns (16 per thread)
+constexpr int kAdjFL = 64;   // outputs per line job of the frame
+constexpr int kAdjFrameLds = 64 * 1024;   // LDS of a frame job: weight and A slabs
 
 struct AdjArgs {
     const float2 *A;
@@ -20,14 +22,15 @@ struct AdjArgs {
     int N, M, P, Q, Kr, Kc;
     int ir0, ir1, ic0, ic1;     // interior outputs [ir0, ir1) x [ic0, ic1)
     int ndc;                    // 2Q-1 rounded up to a multiple of 16
-    int64_t n_frame;            // outputs outside the interior
     double *tables;             // [(2P-1)(2Q-1)][(P+1)(Q+1)] complex FP64 prefix sums
     double *hfull;              // [(2P-1)(2Q-1)] complex FP64 full sums
     int normalize;
     int pad;
 };
 
+// n_frame_jobs: the frame's row, column and corner jobs (adj_frame decodes
+// its job from the block index and the interior bounds)
 hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int n_interior_blocks,
-                          size_t lds_interior, int64_t n_frame, hipStream_t s);
+                          size_t lds_interior, int64_t n_frame_jobs, hipStream_t s);
 
 }  // namespace covest

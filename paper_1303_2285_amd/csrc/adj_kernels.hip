@@ -15,7 +15,12 @@
 //                c in [Q-1, Kc-1]): h is the lag's full sum, so the output is a
 //                2-D correlation of A with a (2P-1) x (2Q-1) kernel; ring walk
 //                over dc with 16 outputs per thread, FP64 accumulators.
-// adj_frame      the remaining outputs: h read from the prefix sums (4 reads).
+// adj_frame      the remaining outputs, h taken from the prefix sums (4 reads):
+//                an output row outside the interior rows, next to interior
+//                columns, has weights that depend on its row only, so a line
+//                of such outputs is again a correlation with one kernel (row
+//                jobs; column jobs likewise); outputs in a border row and a
+//                border column get their own weights (corner jobs).
 #include <hip/hip_runtime.h>
 
 #include "adj_internal.hpp"
@@ -105,50 +110,155 @@ __device__ __forceinline__ void store_da(const AdjArgs &aa, int r, int c, double
     aa.dA[(int64_t)r * aa.ldda + c] = make_float2((float)s.x, (float)s.y);
 }
 
-// D2, frame: one thread per output outside the interior.
+// h_(dr,dc)(r, c) from the lag's prefix table; false (and zero) when no
+// window offset holds (r, c) for this lag.  A non-empty offset range implies
+// that A[r+dr][c+dc] lies inside A.
+__device__ __forceinline__ bool hbox(const AdjArgs &aa, int r, int c, int dr, int dc, double2 &h)
+{
+    const int P = aa.P, Q = aa.Q;
+    const int ilo = max(max(0, -dr), r - aa.Kr + 1), ihi = min(min(P - 1, P - 1 - dr), r);
+    const int jlo = max(max(0, -dc), c - aa.Kc + 1), jhi = min(min(Q - 1, Q - 1 - dc), c);
+    h = dz();
+    if (ilo > ihi || jlo > jhi) return false;
+    const int lag = (dr + P - 1) * (2 * Q - 1) + (dc + Q - 1);
+    const double2 *S = reinterpret_cast<const double2 *>(aa.tables) + (int64_t)lag * (P + 1) * (Q + 1);
+    h = box(S, Q + 1, ilo, ihi, jlo, jhi);
+    return true;
+}
+
+__device__ __forceinline__ double2 block_sum_256(double2 v, double2 *red)
+{
+    // fixed order: a butterfly inside each wave, then the four waves in order
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        v.x += __shfl_xor(v.x, off, 64);
+        v.y += __shfl_xor(v.y, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    double2 s = red[0];
+    for (int w = 1; w < 4; ++w) s = make_double2(s.x + red[w].x, s.y + red[w].y);
+    return s;
+}
+
+// D2, frame.  Jobs, in block order: row jobs (border row r, up to kAdjFL
+// interior columns), column jobs (border column c, up to kAdjFL interior
+// rows), corner jobs (one output in a border row and a border column).
+// A line job computes out[u] = sum_{x, y} T[x][u + y] * W[x][y] with
+//   row job:    x = dr+P-1, y = dc+Q-1, T[x][j] = A[r+dr][c0-(Q-1)+j]
+//   column job: x = dc+Q-1, y = dr+P-1, T[x][j] = A[r0-(P-1)+j][c+dc]
+// staged in LDS in slabs of x; wave w takes x = w, w+4, ... of each slab and
+// the four waves' sums are added in wave order.
 __global__ void __launch_bounds__(256) adj_frame(AdjArgs aa)
 {
-    const int P = aa.P, Q = aa.Q, N = aa.N, M = aa.M, Kr = aa.Kr, Kc = aa.Kc;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= aa.n_frame) return;
-    // frame outputs enumerated row by row: rows outside [ir0, ir1) are whole,
-    // rows inside contribute their columns outside [ic0, ic1)
-    int r, c;
-    {
-        const int ir0 = aa.ir0, ir1 = aa.ir1, ic0 = aa.ic0, ic1 = aa.ic1;
-        const int64_t top = (int64_t)ir0 * M;
-        const int per_mid = M - (ic1 - ic0);
-        const int64_t mid = (int64_t)(ir1 - ir0) * per_mid;
-        if (t < top) {
-            r = (int)(t / M);
-            c = (int)(t % M);
-        } else if (t < top + mid) {
-            const int64_t u = t - top;
-            r = ir0 + (int)(u / per_mid);
-            const int k = (int)(u % per_mid);
-            c = k < ic0 ? k : ic1 + (k - ic0);
-        } else {
-            const int64_t u = t - top - mid;
-            r = ir1 + (int)(u / M);
-            c = (int)(u % M);
+    extern __shared__ double2 sm[];
+    const int P = aa.P, Q = aa.Q, N = aa.N, M = aa.M;
+    const int tid = threadIdx.x;
+    const int nbc = M - (aa.ic1 - aa.ic0);
+    const int nlc = (aa.ic1 - aa.ic0 + kAdjFL - 1) / kAdjFL;
+    const int nlr = (aa.ir1 - aa.ir0 + kAdjFL - 1) / kAdjFL;
+    const int64_t nrow_jobs = (int64_t)(N - (aa.ir1 - aa.ir0)) * nlc;
+    const int64_t ncol_jobs = (int64_t)nbc * nlr;
+    const int64_t job = blockIdx.x;
+    auto band_row = [&](int k) { return k < aa.ir0 ? k : aa.ir1 + (k - aa.ir0); };
+    auto band_col = [&](int k) { return k < aa.ic0 ? k : aa.ic1 + (k - aa.ic0); };
+
+    if (job >= nrow_jobs + ncol_jobs) {
+        // corner job: one output with its own weights, lags spread over the block
+        const int64_t k = job - nrow_jobs - ncol_jobs;
+        const int r = band_row((int)(k / nbc)), c = band_col((int)(k % nbc));
+        const int ndc = 2 * Q - 1, nl = (2 * P - 1) * ndc;
+        double2 s = dz();
+        for (int l = tid; l < nl; l += 256) {
+            const int dr = l / ndc - (P - 1), dc = l % ndc - (Q - 1);
+            double2 h;
+            if (hbox(aa, r, c, dr, dc, h)) {
+                const float2 av = aa.A[(int64_t)(r + dr) * aa.lda + (c + dc)];
+                cmla(s, make_double2(av.x, av.y), h);
+            }
         }
+        s = block_sum_256(s, sm);
+        if (tid == 0) store_da(aa, r, c, s);
+        return;
     }
-    const int w = Q + 1;
-    double2 s = dz();
-    for (int dr = -(P - 1); dr < P; ++dr) {
-        const int ilo = max(max(0, -dr), r - Kr + 1), ihi = min(min(P - 1, P - 1 - dr), r);
-        if (ilo > ihi || r + dr < 0 || r + dr >= N) continue;
-        for (int dc = -(Q - 1); dc < Q; ++dc) {
-            const int jlo = max(max(0, -dc), c - Kc + 1), jhi = min(min(Q - 1, Q - 1 - dc), c);
-            if (jlo > jhi || c + dc < 0 || c + dc >= M) continue;
-            const int lag = (dr + P - 1) * (2 * Q - 1) + (dc + Q - 1);
-            const double2 *S = reinterpret_cast<const double2 *>(aa.tables) + (int64_t)lag * (P + 1) * w;
-            const double2 h = box(S, w, ilo, ihi, jlo, jhi);
-            const float2 av = aa.A[(int64_t)(r + dr) * aa.lda + (c + dc)];
-            cmla(s, make_double2(av.x, av.y), h);
+
+    const bool rowjob = job < nrow_jobs;
+    int r0, c0, len;
+    if (rowjob) {
+        const int k = (int)(job / nlc), ch = (int)(job % nlc);
+        r0 = band_row(k);
+        c0 = aa.ic0 + ch * kAdjFL;
+        len = min(kAdjFL, aa.ic1 - c0);
+    } else {
+        const int64_t j = job - nrow_jobs;
+        const int k = (int)(j / nlr), ch = (int)(j % nlr);
+        c0 = band_col(k);
+        r0 = aa.ir0 + ch * kAdjFL;
+        len = min(kAdjFL, aa.ir1 - r0);
+    }
+    // the weights of every output of the line: those of an interior column
+    // (row job) or an interior row (column job)
+    const int wr = rowjob ? r0 : aa.ir0, wc = rowjob ? aa.ic0 : c0;
+    const int X = rowjob ? 2 * P - 1 : 2 * Q - 1, Y = rowjob ? 2 * Q - 1 : 2 * P - 1;
+    const int span = kAdjFL + Y - 1;
+    const int stride = span | 1;
+    const int XS = max(1, min(X, kAdjFrameLds / (Y * 16 + stride * 8)));
+    double2 *Wt = sm;                                               // XS x Y
+    float2 *Tt = reinterpret_cast<float2 *>(sm + (size_t)XS * Y);   // XS x stride
+    const int u = tid % 64, wv = tid / 64;
+    double2 acc0 = dz(), acc1 = dz();
+    for (int xs = 0; xs < X; xs += XS) {
+        const int xn = min(XS, X - xs);
+        for (int e = tid; e < xn * Y; e += 256) {
+            const int x = xs + e / Y, y = e % Y;
+            const int dr = (rowjob ? x : y) - (P - 1), dc = (rowjob ? y : x) - (Q - 1);
+            double2 h;
+            hbox(aa, wr, wc, dr, dc, h);
+            Wt[e] = h;
         }
+        for (int e = tid; e < xn * span; e += 256) {
+            // neighbouring threads read neighbouring columns of A
+            int xl, j, ar, ac;
+            if (rowjob) {
+                xl = e / span;
+                j = e - xl * span;
+                ar = r0 + xs + xl - (P - 1);
+                ac = c0 - (Q - 1) + j;
+            } else {
+                j = e / xn;
+                xl = e - j * xn;
+                ar = r0 - (P - 1) + j;
+                ac = c0 + xs + xl - (Q - 1);
+            }
+            float2 v = make_float2(0.f, 0.f);
+            if (ar >= 0 && ar < N && ac >= 0 && ac < M) v = aa.A[(int64_t)ar * aa.lda + ac];
+            Tt[xl * stride + j] = v;
+        }
+        __syncthreads();
+        for (int xl = wv; xl < xn; xl += 4) {
+            const float2 *trow = Tt + xl * stride + u;
+            const double2 *wrow = Wt + xl * Y;
+            int y = 0;
+            for (; y + 1 < Y; y += 2) {
+                const float2 t0 = trow[y], t1 = trow[y + 1];
+                cmla(acc0, make_double2(t0.x, t0.y), wrow[y]);
+                cmla(acc1, make_double2(t1.x, t1.y), wrow[y + 1]);
+            }
+            if (y < Y) {
+                const float2 t0 = trow[y];
+                cmla(acc0, make_double2(t0.x, t0.y), wrow[y]);
+            }
+        }
+        __syncthreads();
     }
-    store_da(aa, r, c, s);
+    sm[tid] = make_double2(acc0.x + acc1.x, acc0.y + acc1.y);
+    __syncthreads();
+    if (tid < len) {
+        double2 s = sm[tid];
+        for (int w = 1; w < 4; ++w) s = make_double2(s.x + sm[w * 64 + tid].x, s.y + sm[w * 64 + tid].y);
+        if (rowjob) store_da(aa, r0, c0 + tid, s);
+        else store_da(aa, r0 + tid, c0, s);
+    }
 }
 
 // D2, interior: workgroup tile of kAdjTR rows x kAdjTC columns of outputs.
@@ -234,10 +344,13 @@ __global__ void __launch_bounds__(256) adj_interior(AdjArgs aa)
 }
 
 hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int n_interior_blocks,
-                          size_t lds_interior, int64_t n_frame, hipStream_t s)
+                          size_t lds_interior, int64_t n_frame_jobs, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
+        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_frame),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kAdjFrameLds);
+        if (e0 != hipSuccess) return e0;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_interior),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -254,8 +367,8 @@ hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int 
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (n_frame > 0) {
-        hipLaunchKernelGGL(adj_frame, dim3((unsigned)((n_frame + 255) / 256)), dim3(256), 0, s, aa);
+    if (n_frame_jobs > 0) {
+        hipLaunchKernelGGL(adj_frame, dim3((unsigned)n_frame_jobs), dim3(256), kAdjFrameLds, s, aa);
         e = hipGetLastError();
     }
     return e;
