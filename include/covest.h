@@ -77,11 +77,12 @@ typedef enum {
  * FP64 sums of the same products (each distinct product once, Sec. 3.3); they
  * differ in speed and in the order of the additions. */
 typedef enum {
-    COVEST_ENGINE_AUTO = 0,    /* matrix cores where the window suits them, else vector  */
+    COVEST_ENGINE_AUTO = 0,    /* matrix cores where the window suits them (at least 70%
+                                  of the 16 x 16 tiles' lags real), else vector          */
     COVEST_ENGINE_VECTOR = 1,  /* FP64 FMA on the vector units, lags in a register ring  */
     COVEST_ENGINE_MATRIX = 2   /* FP64 MFMA: per line, a block of A times a Toeplitz band
-                                  of the line; needs N >= 2P-1, M >= 2Q-1 and a lag block
-                                  of at most 8 tiles of 16 x 16 with little padding
+                                  of the line; needs N >= 2P-1, M >= 2Q-1, Q >= 4 and a
+                                  lag block of at most 8 tiles of 16 x 16
                                   (COVEST_ERR_UNSUPPORTED otherwise)                     */
 } covest_engine;
 
@@ -157,7 +158,10 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
  * workspace, and captures the launches into a HIP graph on `stream`.  Every
  * problem uses opts->prec (FP64 or FP32) with the recurrence form.
  * covest_forward_batched replays that graph on `stream`: one launch for every
- * instance.  The A and R buffers named at creation must stay valid. */
+ * instance.  The A and R buffers named at creation must stay valid.
+ * opts->engine applies per problem as for a single call (AUTO: the matrix
+ * cores wherever they fit; MATRIX: an error if some problem does not fit).
+ * Matrix-core problems run in one extra launch per lag-block shape. */
 int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,
                                const covest_opts *opts, hipStream_t stream);
 int covest_forward_batched(covest_plan *plan, hipStream_t stream);

@@ -270,10 +270,10 @@ class BatchedPlan:
     """Many (A, P, Q) problems computed by one graph launch (covest_forward_batched)."""
 
     def __init__(self, problems, precision="fp64", fill="full", normalize=True, ring_cols=0,
-                 ring_rows=0):
+                 ring_rows=0, engine="auto"):
         torch = _torch()
         self._problems = [_Problem(A, int(P), int(Q)) for (A, P, Q) in problems]
-        o = make_opts("recurrence", precision, fill, normalize, ring_cols, ring_rows)
+        o = make_opts("recurrence", precision, fill, normalize, ring_cols, ring_rows, engine)
         rdtype = torch.complex128 if o.prec == 0 else torch.complex64
         arr = (covest_problem * len(self._problems))()
         self.outputs = []

@@ -167,12 +167,13 @@ int n_slots_for_device(int dev) { return 2 * cus_of_device(dev); }
 
 // Engine of the recurrence's main pass for this shape and options: 1 vector,
 // 2 matrix cores, 0 when the requested engine cannot run the shape.
-int pick_engine(int N, int M, int P, int Q, const covest_opts &o)
+// 2: matrix cores, 1: vector units, 0: the forced matrix engine cannot run
+// this shape.  AUTO takes the matrix cores above min_fill.
+int pick_engine(int N, int M, int P, int Q, const covest_opts &o, double min_fill = kMfmaFill)
 {
-    const bool fits = mfma_fits(N, M, P, Q);
-    if (o.engine == COVEST_ENGINE_MATRIX) return fits ? 2 : 0;
+    if (o.engine == COVEST_ENGINE_MATRIX) return mfma_fits(N, M, P, Q) ? 2 : 0;
     if (o.engine == COVEST_ENGINE_VECTOR) return 1;
-    return (fits && o.ring_cols == 0 && o.ring_rows == 0) ? 2 : 1;
+    return (mfma_fits(N, M, P, Q, min_fill) && o.ring_cols == 0 && o.ring_rows == 0) ? 2 : 1;
 }
 
 ShapePlan plan_for(int N, int M, int P, int Q, int cus, int w0, int w1, int engine)
@@ -328,7 +329,7 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     fa.use_inline = 1;
     fa.inst_inline = in;
     HIP_TRY(timed("rec_finalize", stream, [&] {
-        return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, sp.fin_table, stream);
+        return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, sp.fin_variant, stream);
     }));
     return finish_call(stream);
 }
@@ -491,11 +492,19 @@ struct covest_plan {
     Job *d_jobs = nullptr;
     LagGroup *d_groups = nullptr;
     Inst *d_insts = nullptr;
-    FinItem *d_items[2] = {nullptr, nullptr};   // [0] table finalize, [1] per-lane finalize
+    FinItem *d_items[3] = {nullptr, nullptr, nullptr};   // per finalize variant (kFinTable, ...)
     unsigned int *d_counter = nullptr;
     void *d_ws = nullptr;
-    int n_jobs = 0, n_items[2] = {0, 0}, grid = 0;
-    size_t lds_main = 0, lds_fin[2] = {0, 0};
+    int n_jobs = 0, n_items[3] = {0, 0, 0}, grid = 0;
+    size_t lds_main = 0, lds_fin[3] = {0, 0, 0};
+    // matrix-core jobs, one launch per lag-block shape (mt x nt tiles)
+    struct MfmaLaunch {
+        int mt = 0, nt = 0, n_jobs = 0;
+        MJob *d_jobs = nullptr;
+        size_t lds = 0;
+    };
+    std::vector<MfmaLaunch> mfma;
+    int n_matrix = 0;   // problems on the matrix-core engine
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double est_cost = 0.0;
@@ -508,9 +517,12 @@ void free_plan(covest_plan *p)
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void *bufs[] = {p->d_jobs, p->d_groups, p->d_insts, p->d_items[0], p->d_items[1], p->d_counter, p->d_ws};
+    void *bufs[] = {p->d_jobs,     p->d_groups,     p->d_insts,   p->d_items[0],
+                    p->d_items[1], p->d_items[2], p->d_counter, p->d_ws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    for (auto &l : p->mfma)
+        if (l.d_jobs) (void)hipFree(l.d_jobs);
     if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
     delete p;
 }
@@ -601,11 +613,12 @@ int time_main(const ShapePlan &sp, const covest_problem &p, const covest_opts &o
 }
 
 // Widths for every (P, Q) class of the batch.
-int autotune(const covest_problem *pr, int64_t count, const covest_opts &o, int resident,
-             std::map<std::pair<int, int>, std::pair<int, int>> *out)
+int autotune(const covest_problem *pr, int64_t count, const std::vector<int> &engine, const covest_opts &o,
+             int resident, std::map<std::pair<int, int>, std::pair<int, int>> *out)
 {
     std::map<std::pair<int, int>, int64_t> rep;   // class -> representative problem
     for (int64_t i = 0; i < count; ++i) {
+        if (engine[i] != 1) continue;   // only the vector engine has widths to tune
         const auto key = std::make_pair((int)pr[i].P, (int)pr[i].Q);
         auto it = rep.find(key);
         if (it == rep.end() || (int64_t)pr[i].N * pr[i].M > (int64_t)pr[it->second].N * pr[it->second].M)
@@ -662,9 +675,24 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     const int cus = cu_count(plan->device);
     const int resident = 2 * cus;
     HIP_TRY(prepare_rec_kernels());
+    // engine per problem, as for a single call
+    std::vector<int> engine(count);
+    for (int64_t i = 0; i < count; ++i) {
+        int e = pick_engine(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, o);
+        if (e == 0)
+            return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine does not fit %dx%d, %dx%d",
+                        (long long)i, pr[i].N, pr[i].M, pr[i].P, pr[i].Q);
+        if (e == 2 && (int64_t)pr[i].N * pr[i].M + pr[i].M >= ((int64_t)1 << 31)) {
+            if (o.engine == COVEST_ENGINE_MATRIX)
+                return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine needs N * M < 2^31",
+                            (long long)i);
+            e = 1;
+        }
+        engine[i] = e;
+    }
     std::map<std::pair<int, int>, std::pair<int, int>> widths;
     if (!o.ring_cols && !o.ring_rows) {
-        int st = autotune(pr, count, o, resident, &widths);
+        int st = autotune(pr, count, engine, o, resident, &widths);
         if (st != COVEST_OK) return st;
     }
     auto wfor = [&](int P, int Q) {
@@ -672,35 +700,64 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
         auto it = widths.find({P, Q});
         return it == widths.end() ? std::make_pair(0, 0) : it->second;
     };
-    // first pass: cost of every problem with a coarse plan
+    // first pass: cost of every problem with a coarse plan (vector engine:
+    // wave-steps; matrix-core engine: 8-line k-group steps)
     std::vector<double> cost(count, 0.0);
     double total = 0.0;
+    std::map<std::pair<int, int>, double> total_m;   // per matrix-core launch (mt x nt tiles)
+    auto tiles = [&](int64_t i) { return std::make_pair((2 * pr[i].P - 1 + 15) / 16, (pr[i].Q + 15) / 16); };
     for (int64_t i = 0; i < count; ++i) {
         const auto w = wfor(pr[i].P, pr[i].Q);
-        const ShapePlan sp = make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, 1, w.first, w.second);
+        const ShapePlan sp = engine[i] == 2 ? make_mfma_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, 1)
+                                            : make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, 1, w.first, w.second);
         for (double c : sp.job_cost) cost[i] += c;
-        total += cost[i];
+        if (engine[i] == 2) total_m[tiles(i)] += cost[i];
+        else total += cost[i];
     }
-    // second pass: split each problem into jobs of about a third of a resident slot's share
+    // second pass: split each problem into jobs of about a third of a
+    // resident slot's share (the matrix-core kernel holds one workgroup per
+    // CU; each of its launches is balanced on its own)
     const double target = std::max(1.0, total / (3.0 * resident));
     std::vector<Job> jobs;
     std::vector<double> jcost;
     std::vector<LagGroup> groups;
     std::vector<Inst> insts(count);
-    std::vector<FinItem> items[2];
+    std::vector<FinItem> items[3];
     size_t ws_off = 0;
     std::vector<size_t> ws_base(count);
     std::vector<ShapePlan> plans(count);
     for (int64_t i = 0; i < count; ++i) {
-        const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(resident, std::llround(cost[i] / target)));
         const auto w = wfor(pr[i].P, pr[i].Q);
-        plans[i] = make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, slots, w.first, w.second);
+        if (engine[i] == 2) {
+            plans[i] = make_mfma_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, cus,
+                                      std::max(1.0, total_m[tiles(i)] / (3.0 * cus)));
+        } else {
+            const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(resident, std::llround(cost[i] / target)));
+            plans[i] = make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, slots, w.first, w.second);
+        }
         ws_base[i] = ws_off;
         ws_off += (plans[i].ws_bytes + 255) / 256 * 256;
     }
     HIP_TRY(hipMalloc(&plan->d_ws, std::max<size_t>(ws_off, 256)));
+    struct MGroup {
+        std::vector<MJob> jobs;
+        std::vector<double> cost;
+        size_t lds = 0;
+    };
+    std::map<std::pair<int, int>, MGroup> mgroups;   // (mt, nt) -> matrix-core jobs
     for (int64_t i = 0; i < count; ++i) {
         const ShapePlan &sp = plans[i];
+        if (engine[i] == 2) {
+            MGroup &mg = mgroups[{sp.mt, sp.nt}];
+            for (size_t j = 0; j < sp.mjobs.size(); ++j) {
+                MJob mj = sp.mjobs[j];
+                mj.inst = (int)i;
+                mg.jobs.push_back(mj);
+                mg.cost.push_back(sp.job_cost[j]);
+            }
+            mg.lds = std::max(mg.lds, sp.lds_main);
+            ++plan->n_matrix;
+        }
         const int goff = (int)groups.size();
         groups.insert(groups.end(), sp.groups.begin(), sp.groups.end());
         for (size_t j = 0; j < sp.jobs.size(); ++j) {
@@ -710,12 +767,12 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
             jobs.push_back(jb);
             jcost.push_back(sp.job_cost[j]);
         }
-        const int var = sp.fin_table ? 0 : 1;
+        const int var = sp.fin_variant;
         for (FinItem it : sp.items) {
             it.inst = (int)i;
             items[var].push_back(it);
         }
-        plan->lds_main = std::max(plan->lds_main, sp.lds_main);
+        if (engine[i] != 2) plan->lds_main = std::max(plan->lds_main, sp.lds_main);
         plan->lds_fin[var] = std::max(plan->lds_fin[var], sp.lds_fin);
         insts[i] = make_inst(sp, pr[i].A, pr[i].M, pr[i].R, (int64_t)pr[i].P * pr[i].Q,
                              static_cast<char *>(plan->d_ws) + ws_base[i], o);
@@ -729,15 +786,30 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     for (size_t j : order) sorted.push_back(jobs[j]);
     plan->est_cost = total;
     plan->n_jobs = (int)sorted.size();
-    plan->n_items[0] = (int)items[0].size();
-    plan->n_items[1] = (int)items[1].size();
+    for (int v = 0; v < 3; ++v) plan->n_items[v] = (int)items[v].size();
     plan->grid = std::max(1, std::min(resident, plan->n_jobs));
     HIP_TRY(upload(&plan->d_jobs, sorted));
     HIP_TRY(upload(&plan->d_groups, groups));
     HIP_TRY(upload(&plan->d_insts, insts));
-    HIP_TRY(upload(&plan->d_items[0], items[0]));
-    HIP_TRY(upload(&plan->d_items[1], items[1]));
+    for (int v = 0; v < 3; ++v) HIP_TRY(upload(&plan->d_items[v], items[v]));
     HIP_TRY(hipMalloc(&plan->d_counter, 256));
+    for (auto &kv : mgroups) {
+        // longest first: the hardware hands out workgroups in block order
+        MGroup &mg = kv.second;
+        std::vector<size_t> ord(mg.jobs.size());
+        for (size_t j = 0; j < ord.size(); ++j) ord[j] = j;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return mg.cost[a] > mg.cost[b]; });
+        std::vector<MJob> mjs;
+        mjs.reserve(ord.size());
+        for (size_t j : ord) mjs.push_back(mg.jobs[j]);
+        covest_plan::MfmaLaunch l;
+        l.mt = kv.first.first;
+        l.nt = kv.first.second;
+        l.n_jobs = (int)mjs.size();
+        l.lds = mg.lds;
+        plan->mfma.push_back(l);
+        HIP_TRY(upload(&plan->mfma.back().d_jobs, mjs));
+    }
 
     // capture: counter reset + persistent main kernel + finalize kernels
     hipStream_t cs = stream;
@@ -756,14 +828,23 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
         ma.use_inline = 0;
         e = launch_rec_persistent(ma, plan->d_counter, plan->grid, plan->lds_main, cs);
     }
-    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    for (const auto &l : plan->mfma) {
+        if (e != hipSuccess) break;
+        MfmaArgs ma{};
+        ma.jobs = l.d_jobs;
+        ma.n_jobs = l.n_jobs;
+        ma.xcd_remap = 0;
+        ma.insts = plan->d_insts;
+        e = launch_rec_mfma(ma, l.mt, l.nt, l.n_jobs, l.lds, cs);
+    }
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
         if (plan->n_items[v] == 0) continue;
         FinArgs fa{};
         fa.items = plan->d_items[v];
         fa.insts = plan->d_insts;
         fa.n_items = plan->n_items[v];
         fa.use_inline = 0;
-        e = launch_rec_finalize(fa, plan->n_items[v], plan->lds_fin[v], v == 0, cs);
+        e = launch_rec_finalize(fa, plan->n_items[v], plan->lds_fin[v], v, cs);
     }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);

@@ -27,6 +27,10 @@ namespace covest {
 constexpr int kWaves = 4;          // waves per workgroup of the main kernel
 constexpr int kThreads = 64 * kWaves;
 constexpr int kFinMaxRows = 160;   // individual rows the table finalize handles (n_ir)
+// finalize variants: LDS table (16 corner loads per thread in flight), one
+// wave per combination, LDS table for at most kFinSmallCorners corner products
+enum { kFinTable = 0, kFinLean = 1, kFinTableSmall = 2 };
+constexpr int kFinSmallCorners = 4 * 256;
 
 // A set of lanes of one wave slot: lane li has
 //   d1 = d1lo + li / nch,   d2 chunk start = ch0 + (li % nch) * W
@@ -150,6 +154,7 @@ struct MfmaArgs {
     const MJob *jobs;
     int n_jobs;
     int xcd_remap;
+    const Inst *insts;   // batches: job.inst indexes this table; single problems: null, inst below
     Inst inst;
 };
 

@@ -12,7 +12,8 @@ hipError_t prepare_rec_kernels();
 hipError_t launch_rec_main(const MainArgs &ma, int n_blocks, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_rec_persistent(const MainArgs &ma, unsigned int *counter, int n_blocks, size_t lds_bytes,
                                  hipStream_t stream);
-hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
+// variant: kFinTable, kFinTableSmall (plan.hpp) or kFinLean
+hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, int variant,
                                hipStream_t stream);
 
 // Matrix-core main pass (rec_mfma.hip): mt x nt tiles of the orientation-0 lag block.

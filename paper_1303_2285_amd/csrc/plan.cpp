@@ -95,8 +95,9 @@ static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
         }
     }
     const size_t table = (size_t)(1 + sp.n_ir) * (sp.n_ic | 1) * 16;
-    sp.fin_table = table <= kFinTableMax && sp.n_ir <= kFinMaxRows;
-    sp.lds_fin = sp.fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
+    const bool fin_table = table <= kFinTableMax && sp.n_ir <= kFinMaxRows;
+    sp.fin_variant = !fin_table ? kFinLean : sp.n_ir * sp.n_ic <= kFinSmallCorners ? kFinTableSmall : kFinTable;
+    sp.lds_fin = fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
 
     sp.ws_bytes = (size_t)16 * sp.lag_stride *
                   ((size_t)sp.n_bulk + (size_t)sp.zpieces * ((size_t)sp.n_ir + (size_t)sp.n_ic));
@@ -295,15 +296,15 @@ ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0, int w
 }
 
 
-bool mfma_fits(int N, int M, int P, int Q)
+bool mfma_fits(int N, int M, int P, int Q, double min_fill)
 {
     if (N - 2 * P + 2 < 1 || M - 2 * Q + 2 < 1 || Q < 4) return false;
     const int mt = (2 * P - 1 + 15) / 16, nt = (Q + 15) / 16;
     if (mt * nt > 8) return false;
-    return (double)(2 * P - 1) * Q >= 0.7 * 256.0 * mt * nt;
+    return (double)(2 * P - 1) * Q >= min_fill * 256.0 * mt * nt;
 }
 
-ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
+ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units)
 {
     ShapePlan sp;
     sp.engine = 2;
@@ -351,7 +352,7 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
         strip_len = std::max(strip_len, nkg[b.orient]);
         strip_min = std::min(strip_min, nkg[b.orient]);
     }
-    const double ideal = ((double)U + strip_total) / n_cu;
+    const double ideal = job_units > 0.0 ? job_units : ((double)U + strip_total) / n_cu;
     // pieces per strip line: a piece no longer than a balanced share, and no
     // piece empty (the finalize adds every piece's row, so each is written)
     sp.zpieces = 1;
@@ -385,7 +386,8 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu)
 
     const int n_strip = (int)strips.size();
     int n_bulk;
-    if (n_strip < n_cu && smax <= 1.1 * ideal) n_bulk = n_cu - n_strip;
+    if (job_units > 0.0) n_bulk = (int)std::ceil((double)U / ideal);
+    else if (n_strip < n_cu && smax <= 1.1 * ideal) n_bulk = n_cu - n_strip;
     else n_bulk = (int)std::ceil((double)U / std::max((double)smax, ideal));
     n_bulk = (int)std::max<int64_t>(1, std::min<int64_t>(n_bulk, std::max<int64_t>(1, U / 4)));
     sp.n_bulk = n_bulk;

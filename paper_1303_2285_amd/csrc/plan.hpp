@@ -35,7 +35,7 @@ struct ShapePlan {
     std::vector<FinItem> items;
     std::vector<double> job_cost;        // estimated wave-steps per job
     size_t lds_main = 0, lds_fin = 0;
-    bool fin_table = false;              // finalize through the LDS table variant
+    int fin_variant = 1;                 // kFinTable, kFinLean or kFinTableSmall
     size_t ws_bytes = 0;                 // partial + zr + zc, FP64 complex
     int64_t main_products = 0;           // distinct products the main kernel keeps
     int64_t fin_products = 0;            // corner products the finalize computes
@@ -50,12 +50,15 @@ struct ShapePlan {
 ShapePlan make_shape_plan(int N, int M, int P, int Q, int n_slots, int w0 = 0, int w1 = 0);
 
 // Matrix-core plan: one workgroup of kMWaves waves per compute unit (n_cu).
-// Valid when mfma_fits(N, M, P, Q).
-ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu);
+// Valid when mfma_fits(N, M, P, Q).  job_units > 0 (batches): jobs of about
+// that many 8-line k-group steps instead of one job per compute unit.
+ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units = 0.0);
 
-// The matrix-core engine needs a non-empty middle block, a lag block of at
-// most 8 tiles (one wave holds all its sums) and little tile padding.
-bool mfma_fits(int N, int M, int P, int Q);
+// The matrix-core engine needs a non-empty middle block and a lag block of at
+// most 8 tiles (one wave holds all its sums); min_fill: the least share of
+// the tiles' lags that are real (0: any).
+constexpr double kMfmaFill = 0.7;   // AUTO chooses the matrix cores above this
+bool mfma_fits(int N, int M, int P, int Q, double min_fill = 0.0);
 
 // Ring widths worth trying for a window extent n (the first is the default).
 std::vector<int> ring_width_candidates(int n);

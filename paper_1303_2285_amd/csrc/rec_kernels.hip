@@ -422,7 +422,11 @@ __device__ __forceinline__ double2 lds_chain(double2 s, const double2 *t, int lo
 // product the sliding needs is computed at once into an LDS table (rows:
 // the middle class and each individual row; columns: the individual columns),
 // so the loads overlap instead of forming one long dependent chain per lane.
-// The sums run in the same order as rec_finalize.
+// The sums run in the same order as rec_finalize.  kFinBatch: corner loads
+// per thread in flight; kFinChunk: offsets per thread in the two slides.
+// Small tables take <4, 4>, which needs fewer registers, so that more
+// workgroups share a CU.
+template <int kFinBatch, int kFinChunk>
 __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 {
     extern __shared__ double2 V[];
@@ -454,7 +458,6 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     // lag's bulk partials (two per thread, more in a loop if there are
     // more), its column- and row-strip sums and the first kFinBatch corner
     // products of each thread; so the item waits for about one load latency.
-    constexpr int kFinBatch = 16;
     const int ncorner = (ncls - 1) * nV;
     float2 xs[kFinBatch], ys[kFinBatch];
     bool ok[kFinBatch];
@@ -520,7 +523,6 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     // direct sum and slides across the chunk (one column leaves, one enters);
     // results are written in place over the consumed left-column terms after
     // a barrier.
-    constexpr int kFinChunk = 8;
     const int nchunk_b = (nc + kFinChunk - 1) / kFinChunk;
     const int cls_per = 256 / nchunk_b;   // whole classes per pass: a class is never split
     for (int cbase = 0; cbase < ncls; cbase += cls_per) {
@@ -608,7 +610,8 @@ hipError_t prepare_rec_kernels()
         const void *fns[] = {reinterpret_cast<const void *>(&rec_main),
                              reinterpret_cast<const void *>(&rec_main_persistent),
                              reinterpret_cast<const void *>(&rec_finalize),
-                             reinterpret_cast<const void *>(&rec_finalize_tab)};
+                             reinterpret_cast<const void *>(&rec_finalize_tab<16, 8>),
+                             reinterpret_cast<const void *>(&rec_finalize_tab<4, 4>)};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
             if (e != hipSuccess) return e;
@@ -638,13 +641,15 @@ hipError_t launch_rec_persistent(const MainArgs &ma, unsigned int *counter, int 
     return hipGetLastError();
 }
 
-hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, bool table,
+hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes, int variant,
                                hipStream_t stream)
 {
     hipError_t e = prepare_rec_kernels();
     if (e != hipSuccess) return e;
-    if (table)
-        hipLaunchKernelGGL(rec_finalize_tab, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    if (variant == kFinTable)
+        hipLaunchKernelGGL((rec_finalize_tab<16, 8>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else if (variant == kFinTableSmall)
+        hipLaunchKernelGGL((rec_finalize_tab<4, 4>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else
         hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
     return hipGetLastError();

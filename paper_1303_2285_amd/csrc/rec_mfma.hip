@@ -93,21 +93,30 @@ __device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const fl
     };
 }
 
-// Run k-groups [k_a, k_b): the next k-group's loads are issued before this
-// one's products, so they overlap (the last iteration reloads its own
+// Run k-groups [k_a, k_b): the loads of k-group kg + D are issued before
+// kg's products, so they overlap (the last iterations reload the last
 // k-group: harmless); the scheduling barriers keep the compiler from moving
-// the loads back behind the conversions.
+// the loads back behind the conversions.  A k-group of MT * NT tiles takes
+// 4 MT NT MFMAs, so small lag blocks keep more k-groups in flight (D) to
+// cover the load latency.
 template <int MT, int NT, class Load>
 __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], Load load)
 {
-    float2 an[MT], xn[NT];
-    load(k_a, an, xn);
-    for (int kg = k_a; kg < k_b; ++kg) {
-        auto mf = kgroup_products<MT, NT>(an, xn);
-        __builtin_amdgcn_sched_barrier(0);
-        load(min(kg + 1, k_b - 1), an, xn);
-        __builtin_amdgcn_sched_barrier(0);
-        mf(acc);
+    constexpr int D = MT * NT >= 8 ? 1 : MT * NT >= 4 ? 2 : 4;
+    float2 an[D][MT], xn[D][NT];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(min(k_a + d, k_b - 1), an[d], xn[d]);
+    for (int kg = k_a; kg < k_b; kg += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (D == 1 || kg + d < k_b) {
+                auto mf = kgroup_products<MT, NT>(an[d], xn[d]);
+                __builtin_amdgcn_sched_barrier(0);
+                load(min(kg + d + D, k_b - 1), an[d], xn[d]);
+                __builtin_amdgcn_sched_barrier(0);
+                mf(acc);
+            }
+        }
     }
 }
 
@@ -282,27 +291,42 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 }
 
 // One workgroup per job; orientation-1 jobs use the transposed tile shape
-// (their d1 runs over Q column lags, d2 over 2P-1 row lags).
-template <int MT, int NT>
+// (their d1 runs over Q column lags, d2 over 2P-1 row lags).  BATCH: the
+// job's problem comes from the instance table (jobs of many problems, longest
+// first, in one launch).
+template <int MT, int NT, bool BATCH>
 __global__ void __launch_bounds__(kMThreads, 2) rec_mfma(MfmaArgs ma)
 {
     extern __shared__ double red[];
     int b = blockIdx.x;
     if (ma.xcd_remap) b = xcd_block(b, ma.n_jobs);
     const MJob job = ma.jobs[b];
-    const Inst &in = ma.inst;
-    if (job.orient == 0) mfma_job<MT, NT, 0>(job, in, red);
-    else mfma_job<NT, MT, 1>(job, in, red);
+    if constexpr (BATCH) {
+        const Inst in = ma.insts[job.inst];
+        if (job.orient == 0) mfma_job<MT, NT, 0>(job, in, red);
+        else mfma_job<NT, MT, 1>(job, in, red);
+    } else {
+        const Inst &in = ma.inst;
+        if (job.orient == 0) mfma_job<MT, NT, 0>(job, in, red);
+        else mfma_job<NT, MT, 1>(job, in, red);
+    }
+}
+
+template <int MT, int NT, bool BATCH>
+static hipError_t launch_mt_nt_b(const MfmaArgs &ma, int n_blocks, size_t lds, hipStream_t stream)
+{
+    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_mfma<MT, NT, BATCH>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((rec_mfma<MT, NT, BATCH>), dim3(n_blocks), dim3(kMThreads), lds, stream, ma);
+    return hipGetLastError();
 }
 
 template <int MT, int NT>
 static hipError_t launch_mt_nt(const MfmaArgs &ma, int n_blocks, size_t lds, hipStream_t stream)
 {
-    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&rec_mfma<MT, NT>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((rec_mfma<MT, NT>), dim3(n_blocks), dim3(kMThreads), lds, stream, ma);
-    return hipGetLastError();
+    if (ma.insts) return launch_mt_nt_b<MT, NT, true>(ma, n_blocks, lds, stream);
+    return launch_mt_nt_b<MT, NT, false>(ma, n_blocks, lds, stream);
 }
 
 hipError_t launch_rec_mfma(const MfmaArgs &ma, int mt, int nt, int n_blocks, size_t lds, hipStream_t stream)

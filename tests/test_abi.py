@@ -61,8 +61,12 @@ def test_workspace_query_errors():
     bad.engine = 3
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     assert "engine" in L.covest_last_error().decode()
-    # the matrix-core engine: not for an 8 x 8 window; its own plan for 32 x 32
-    assert L.covest_workspace_size(64, 64, 8, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    # the matrix-core engine: not where its kernel cannot run (Q < 4, N < 2P - 1);
+    # its own plan where it can, also for an 8 x 8 window that AUTO leaves to the vector units
+    assert L.covest_workspace_size(64, 64, 8, 3, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    assert L.covest_workspace_size(64, 64, 40, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    assert L.covest_workspace_size(64, 64, 8, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.OK
+    assert n.value == cv.mfma_plan(64, 64, 8, 8)[0]["ws_bytes"]
     assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(engine="matrix"), ctypes.byref(n)) == cv.OK
     assert n.value == cv.mfma_plan(1024, 1024, 32, 32)[0]["ws_bytes"]
     assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(engine="vector"), ctypes.byref(n)) == cv.OK

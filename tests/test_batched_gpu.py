@@ -126,6 +126,58 @@ def test_batch_fp32_upper(cv, tdev, oracle_mod):
     plan.close()
 
 
+def fit_int_batch(n, seed):
+    """Small-integer problems, most of which fit the matrix-core engine."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        P = int(rng.choice([8, 12, 16, 24]))
+        Q = int(rng.choice([8, 12, 16, 32]))
+        N = int(rng.integers(2 * P - 1, 2 * P + 150))
+        M = int(rng.integers(2 * Q - 1, 2 * Q + 150))
+        out.append((synth.small_int(N, M, seed=seed * 1000 + i), P, Q))
+    return out
+
+
+@pytest.mark.parametrize("engine", ["auto", "vector"])
+def test_batch_engines_bit_exact(cv, tdev, oracle_mod, engine):
+    """Mixed batches: with engine auto the problems that fit go to the
+    matrix-core kernel (one launch per lag-block shape), the rest to the
+    vector kernel; every result is the oracle's, bit for bit."""
+    torch, dev = tdev
+    batch = fit_int_batch(36, 21)
+    _note("batched integer x36, engine", engine)
+    plan = cv.BatchedPlan([(torch.from_numpy(A).to(dev), P, Q) for (A, P, Q) in batch], engine=engine)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    thr = oracle_mod.max_threads()
+    for (A, P, Q), R in zip(batch, outs):
+        ref = oracle_mod.forward(A, P, Q, threads=thr)
+        got = R.cpu().numpy()
+        assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag), (A.shape, P, Q)
+    plan.close()
+
+
+def test_batch_matrix_engine_forced(cv, tdev, oracle_mod):
+    torch, dev = tdev
+    batch = [(synth.gaussian(70, 90, seed=1), 16, 16), (synth.gaussian(120, 64, seed=2), 24, 16),
+             (synth.gaussian(200, 220, seed=3), 16, 32)]
+    _note("batched matrix engine forced x3")
+    plan = cv.BatchedPlan([(torch.from_numpy(A).to(dev), P, Q) for (A, P, Q) in batch], engine="matrix")
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for (A, P, Q), R in zip(batch, outs):
+        ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
+        got = R.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
+        assert np.array_equal(got, got.conj().T)
+    plan.close()
+    with pytest.raises(cv.CovestError) as e:   # Q < 4: no matrix-core kernel for it
+        cv.BatchedPlan([(torch.zeros((64, 64), dtype=torch.complex64, device=dev), 16, 16),
+                        (torch.zeros((64, 64), dtype=torch.complex64, device=dev), 4, 3)], engine="matrix")
+    assert e.value.status == cv.ERR_UNSUPPORTED
+
+
 def test_batch_errors(cv, tdev):
     torch, dev = tdev
     with pytest.raises(cv.CovestError):

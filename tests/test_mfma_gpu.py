@@ -130,6 +130,21 @@ def test_matrix_engine_deterministic(cv, torch_dev):
 def test_matrix_engine_unsupported_shape(cv, torch_dev):
     torch, dev = torch_dev
     At = torch.zeros((64, 64), dtype=torch.complex64, device=dev)
-    with pytest.raises(cv.CovestError) as e:
-        cv.covest_forward(At, 8, 8, engine="matrix")
-    assert e.value.status == cv.ERR_UNSUPPORTED
+    for P, Q in [(40, 8), (8, 3), (48, 48)]:
+        with pytest.raises(cv.CovestError) as e:
+            cv.covest_forward(At, P, Q, engine="matrix")
+        assert e.value.status == cv.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 8, 8), (90, 70, 12, 12), (15, 7, 8, 4), (40, 200, 4, 16),
+                                   (120, 40, 16, 4)], ids=lambda s: "x".join(map(str, s)))
+def test_matrix_engine_low_fill_bit_exact(cv, torch_dev, oracle_mod, shape):
+    """Windows whose lag block fills its 16 x 16 tiles poorly (the automatic
+    choice keeps them on the vector units for single problems): forced onto
+    the matrix cores they still give the oracle's result bit for bit."""
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=3 * N + M)
+    _note("matrix engine low fill", shape)
+    R = run(cv, torch_dev, A, P, Q, engine="matrix")
+    ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)

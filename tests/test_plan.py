@@ -312,13 +312,16 @@ def test_decomposition_reproduces_oracle(oracle_mod, shape):
 # ---------------------------------------------------------------------------
 
 MFMA_SHAPES = [(1024, 1024, 32, 32), (256, 256, 16, 16), (512, 512, 16, 16), (40, 36, 16, 16),
-               (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16), (34, 64, 16, 32), (300, 64, 28, 28)]
+               (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16), (34, 64, 16, 32), (300, 64, 28, 28),
+               (64, 64, 8, 8), (15, 7, 8, 4), (90, 70, 12, 12)]
 
 
 def test_mfma_fits():
-    for shape in [(1024, 1024, 32, 32), (256, 256, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16)]:
+    # the planner takes any shape the kernel can run (tile padding only costs speed)
+    for shape in [(1024, 1024, 32, 32), (256, 256, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16),
+                  (64, 64, 8, 8), (256, 256, 12, 12), (15, 7, 8, 4)]:
         cv.mfma_plan(*shape)
-    for shape in [(64, 64, 8, 8), (256, 256, 12, 12), (300, 300, 48, 48), (30, 40, 16, 16), (40, 30, 16, 16)]:
+    for shape in [(300, 300, 48, 48), (30, 40, 16, 16), (40, 30, 16, 16), (64, 64, 8, 3), (14, 7, 8, 4)]:
         with pytest.raises(cv.CovestError) as e:
             cv.mfma_plan(*shape)
         assert e.value.status == cv.ERR_UNSUPPORTED, shape
