@@ -459,27 +459,37 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     // more), its column- and row-strip sums and the first kFinBatch corner
     // products of each thread; so the item waits for about one load latency.
     const int ncorner = (ncls - 1) * nV;
+    // corner e -> (individual row rho, individual column gi): floor((e + 1/2) / nV)
+    // in float is exact for every used e (a quotient below n_ir <= 160 carries
+    // an error below 161 * 2^-23 < 2^-15; its distance to an integer is at
+    // least 1/(2 nV) >= 2^-14, as the table holds at most 6144 entries), and
+    // much cheaper than an integer division by a run-time value
+    const float rcp_nV = 1.0f / (float)nV;
+    auto corner_rho = [&](int e) { return (int)fmaf((float)e, rcp_nV, 0.5f * rcp_nV); };
     float2 xs[kFinBatch], ys[kFinBatch];
     bool ok[kFinBatch];
+    const int64_t lag_off = (int64_t)dr * in.lda + dc;
     auto corner_loads = [&](int e0) {
 #pragma unroll
         for (int k = 0; k < kFinBatch; ++k) {
             const int e = e0 + k * 256;
-            const int rho = e / nV, gi = e - rho * nV;
+            const int rho = corner_rho(e), gi = e - rho * nV;
             const int c = gi < Cm0 ? gi : Cm1 + (gi - Cm0);
             const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
             ok[k] = e < ncorner && c + dc < M && r >= rlo && r < rhi;
             const int rr = ok[k] ? r : rlo, cc = ok[k] ? c : 0;
-            xs[k] = A[(int64_t)rr * in.lda + cc];
-            ys[k] = A[(int64_t)(rr + dr) * in.lda + cc + dc];
+            const int64_t off = (int64_t)rr * in.lda + cc;
+            xs[k] = A[off];
+            ys[k] = A[off + lag_off];
         }
     };
     auto corner_store = [&](int e0) {
 #pragma unroll
         for (int k = 0; k < kFinBatch; ++k) {
             const int e = e0 + k * 256;
+            const int rho = corner_rho(e);
             if (e < ncorner)
-                V[(1 + e / nV) * nVs + e % nV] =
+                V[(1 + rho) * nVs + (e - rho * nV)] =
                     ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
                           : make_double2(0.0, 0.0);
         }
