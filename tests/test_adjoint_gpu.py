@@ -62,6 +62,25 @@ def test_adjoint_vs_oracle_small(cv, tdev, oracle_mod, shape):
     assert rel(dA.cpu().numpy().astype(np.complex128), ref) <= 1e-6
 
 
+@pytest.mark.parametrize("shape", [(100, 90, 32, 32), (110, 110, 48, 48), (70, 260, 5, 31), (300, 40, 20, 3)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_wide_windows(cv, tdev, oracle_mod, shape):
+    """Windows whose border jobs stage the weight and A slabs in several
+    passes (32 x 32 with interior; 48 x 48, where the interior kernel's LDS
+    would not fit and every output is a one-output border job) and thin
+    borders on one side only, against the oracle's BLAS adjoint."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    rng = np.random.default_rng(N + M + P)
+    A = synth.gaussian(N, M, seed=N * 3 + M)
+    G = (rng.standard_normal((P * Q, P * Q)) + 1j * rng.standard_normal((P * Q, P * Q))).astype(np.complex64)
+    _note("adjoint wide window", shape)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q)
+    torch.cuda.synchronize()
+    ref = oracle_mod.adjoint_blas(A, G, P, Q)
+    assert rel(dA.cpu().numpy().astype(np.complex128), ref) <= 1e-6
+
+
 def test_adjoint_unnormalized(cv, tdev, oracle_mod):
     torch, dev = tdev
     A = synth.gaussian(15, 17, seed=2)

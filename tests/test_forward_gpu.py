@@ -151,6 +151,24 @@ def test_edge_shapes_gaussian(cv, torch_dev, oracle_mod, shape):
     assert relF(R, ref) <= TOL_FP64
 
 
+def test_largest_window_sampled(cv, torch_dev, oracle_mod):
+    """P = Q = 64, the largest window the recurrence takes (PQ = 4096): sampled
+    entries against the oracle's one-entry sums, R Hermitian, real diagonal."""
+    torch, dev = torch_dev
+    N, M, P, Q = 200, 180, 64, 64
+    A = synth.gaussian(N, M, seed=64)
+    _note("largest window 200x180 P=Q=64")
+    R = cv.covest_forward(torch.from_numpy(A).to(dev), P, Q).cpu().numpy()
+    rng = np.random.default_rng(64)
+    k1 = np.concatenate([rng.integers(0, P * Q, 300), [0, P * Q - 1, 0]])
+    k2 = np.concatenate([rng.integers(0, P * Q, 300), [P * Q - 1, 0, 0]])
+    ref = oracle_mod.entries(A, P, Q, k1, k2, threads=oracle_mod.max_threads())
+    scale = np.abs(np.diag(R)).max()
+    assert np.abs(R[k1, k2] - ref).max() <= 1e-12 * scale
+    assert np.array_equal(R, R.conj().T)
+    assert np.all(np.diag(R).imag == 0)
+
+
 def test_fill_upper_leaves_lower(cv, torch_dev, oracle_mod):
     torch, dev = torch_dev
     A = synth.small_int(48, 40, seed=3)
