@@ -492,11 +492,11 @@ struct covest_plan {
     Job *d_jobs = nullptr;
     LagGroup *d_groups = nullptr;
     Inst *d_insts = nullptr;
-    FinItem *d_items[3] = {nullptr, nullptr, nullptr};   // per finalize variant (kFinTable, ...)
+    FinItem *d_items[kFinVariants] = {};   // per finalize variant (kFinTable, ...)
     unsigned int *d_counter = nullptr;
     void *d_ws = nullptr;
-    int n_jobs = 0, n_items[3] = {0, 0, 0}, grid = 0;
-    size_t lds_main = 0, lds_fin[3] = {0, 0, 0};
+    int n_jobs = 0, n_items[kFinVariants] = {}, grid = 0;
+    size_t lds_main = 0, lds_fin[kFinVariants] = {};
     // matrix-core jobs, one launch per lag-block shape (mt x nt tiles)
     struct MfmaLaunch {
         int mt = 0, nt = 0, n_jobs = 0;
@@ -517,9 +517,10 @@ void free_plan(covest_plan *p)
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void *bufs[] = {p->d_jobs,     p->d_groups,     p->d_insts,   p->d_items[0],
-                    p->d_items[1], p->d_items[2], p->d_counter, p->d_ws};
+    void *bufs[] = {p->d_jobs, p->d_groups, p->d_insts, p->d_counter, p->d_ws};
     for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (FinItem *b : p->d_items)
         if (b) (void)hipFree(b);
     for (auto &l : p->mfma)
         if (l.d_jobs) (void)hipFree(l.d_jobs);
@@ -722,7 +723,7 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     std::vector<double> jcost;
     std::vector<LagGroup> groups;
     std::vector<Inst> insts(count);
-    std::vector<FinItem> items[3];
+    std::vector<FinItem> items[kFinVariants];
     size_t ws_off = 0;
     std::vector<size_t> ws_base(count);
     std::vector<ShapePlan> plans(count);
@@ -786,12 +787,12 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     for (size_t j : order) sorted.push_back(jobs[j]);
     plan->est_cost = total;
     plan->n_jobs = (int)sorted.size();
-    for (int v = 0; v < 3; ++v) plan->n_items[v] = (int)items[v].size();
+    for (int v = 0; v < kFinVariants; ++v) plan->n_items[v] = (int)items[v].size();
     plan->grid = std::max(1, std::min(resident, plan->n_jobs));
     HIP_TRY(upload(&plan->d_jobs, sorted));
     HIP_TRY(upload(&plan->d_groups, groups));
     HIP_TRY(upload(&plan->d_insts, insts));
-    for (int v = 0; v < 3; ++v) HIP_TRY(upload(&plan->d_items[v], items[v]));
+    for (int v = 0; v < kFinVariants; ++v) HIP_TRY(upload(&plan->d_items[v], items[v]));
     HIP_TRY(hipMalloc(&plan->d_counter, 256));
     for (auto &kv : mgroups) {
         // longest first: the hardware hands out workgroups in block order
@@ -837,7 +838,7 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
         ma.insts = plan->d_insts;
         e = launch_rec_mfma(ma, l.mt, l.nt, l.n_jobs, l.lds, cs);
     }
-    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+    for (int v = 0; v < kFinVariants && e == hipSuccess; ++v) {
         if (plan->n_items[v] == 0) continue;
         FinArgs fa{};
         fa.items = plan->d_items[v];

@@ -98,6 +98,16 @@ static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
     const bool fin_table = table <= kFinTableMax && sp.n_ir <= kFinMaxRows;
     sp.fin_variant = !fin_table ? kFinLean : sp.n_ir * sp.n_ic <= kFinSmallCorners ? kFinTableSmall : kFinTable;
     sp.lds_fin = fin_table ? table : (size_t)(1 + sp.n_ir) * Q * 16;
+    // wave prefix sums: an individual column per lane in the row pass, an
+    // individual row per lane in the column pass; LDS holds the classes'
+    // sums per column offset.  Its cost per combination only pays for large
+    // corner tables (measured: 55 -> 50 us at 1024^2 / 32 x 32, 62 x 62
+    // corners; tables of up to ~45 x 45, as in a batch of 4..16 windows, run
+    // slower than with the table variants)
+    if (sp.n_ic <= 64 && sp.n_ir <= 63 && sp.n_ir * sp.n_ic > 2 * kFinSmallCorners) {
+        sp.fin_variant = kFinScan;
+        sp.lds_fin = (size_t)Q * ((1 + sp.n_ir) | 1) * 16;
+    }
 
     sp.ws_bytes = (size_t)16 * sp.lag_stride *
                   ((size_t)sp.n_bulk + (size_t)sp.zpieces * ((size_t)sp.n_ir + (size_t)sp.n_ic));

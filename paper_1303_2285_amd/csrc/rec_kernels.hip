@@ -607,6 +607,156 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, in a fixed order: three
+// shifts inside each row of 16 lanes give sums of 4, two masked shifts
+// complete the rows, two row broadcasts carry the row totals.  Lanes a shift
+// does not reach add zero.
+template <int CTRL, int RMASK, int BMASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RMASK, BMASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RMASK, BMASK, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_scan(double v)
+{
+    double s = v + dpp_f64<0x111, 0xf, 0xf>(v);   // row_shr:1
+    s += dpp_f64<0x112, 0xf, 0xf>(v);             // row_shr:2
+    s += dpp_f64<0x113, 0xf, 0xf>(v);             // row_shr:3
+    s += dpp_f64<0x114, 0xf, 0xe>(s);             // row_shr:4, lanes 4-15 of a row
+    s += dpp_f64<0x118, 0xf, 0xc>(s);             // row_shr:8, lanes 8-15 of a row
+    s += dpp_f64<0x142, 0xa, 0xf>(s);             // row_bcast:15 into rows 1 and 3
+    s += dpp_f64<0x143, 0xc, 0xf>(s);             // row_bcast:31 into rows 2 and 3
+    return s;
+}
+
+__device__ __forceinline__ double2 wave_scan(double2 v) { return make_double2(wave_scan(v.x), wave_scan(v.y)); }
+
+// value of P at lane i (all lanes take part), zero for i < 0
+__device__ __forceinline__ double2 lane_at(double2 p, int i)
+{
+    const int j = max(i, 0);
+    const double2 v = make_double2(__shfl(p.x, j, 64), __shfl(p.y, j, 64));
+    return i < 0 ? make_double2(0.0, 0.0) : v;
+}
+
+// Wave-scan variant of the finalize (256 threads, one unique combination;
+// at most 64 individual columns and 63 individual rows).  Entry (a, b) of
+// the lag's segments is the sum over a box that contains the middle block:
+// the middle sum, plus for the middle rows (class 0) and every individual
+// row inside the box (classes 1..) the row's strip sum and its terms in the
+// individual columns inside the box.  The individual columns inside the box
+// for offset b are one contiguous range [glo, ghi) of the individual-column
+// order, the rows for offset a likewise [ra, rb) (see span), so
+//   row pass:    each wave takes classes in turn, one individual column per
+//                lane: a prefix sum over the lanes gives, for lane b, the
+//                class's sum over [glo(b), ghi(b)) from two lanes of it;
+//   column pass: each wave takes offsets b in turn, one individual row per
+//                lane: a prefix sum over the lanes gives, for lane a, the sum
+//                over the rows [ra(a), rb(a)).
+// Only the classes' sums per offset live in LDS (nc x (1 + n_ir)); the corner
+// products never do.  Rows and columns a lag cannot use are zeroed before
+// the sums, so the differences of prefix sums cancel exactly what they should.
+__global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
+{
+    constexpr int kCls = 16;   // classes per wave at most (64 / 4 waves)
+    extern __shared__ double2 St[];
+    __shared__ double2 red[4];
+    const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
+    const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
+    const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
+    const int dr = it.dr, dc = it.dc;
+    const int lag = (dr + P - 1) * in.Q + dc;
+    const int64_t ls2 = (int64_t)in.lag_stride;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rlo = max(0, -dr), rhi = N - max(0, dr);
+    const int nr = P - abs(dr);
+    const int nc = in.Q - dc;
+    const int Rm0 = in.Rm0, Rm1 = in.Rm1, Cm0 = in.Cm0, Cm1 = in.Cm1;
+    const bool has_mr = Rm1 > Rm0, has_mc = Cm1 > Cm0;
+    const int nir = in.n_ir, nic = in.n_ic, ncls = 1 + nir;
+    const int sst = ncls | 1;   // row stride of the classes' sums (odd: no bank conflicts)
+    const double2 *partial = reinterpret_cast<const double2 *>(in.partial);
+    const double2 *zr = reinterpret_cast<const double2 *>(in.zr);
+    const double2 *zc = reinterpret_cast<const double2 *>(in.zc);
+    const float2 *A = static_cast<const float2 *>(in.A);
+    auto span = [](int x0, int n, int m0, int m1, int &lo, int &hi) {
+        lo = x0 < m0 ? x0 : m0 + max(0, x0 - m1);
+        hi = x0 + n > m1 ? m0 + x0 + n - m1 : min(m0, x0 + n);
+    };
+
+    // Every global load goes out first: the bulk partials, this wave's
+    // corner pairs (lane = individual column) and, in wave 0, the middle
+    // rows' column strips.
+    const int g = lane;
+    const int c = g < Cm0 ? g : Cm1 + (g - Cm0);
+    const bool col_ok = g < nic && c + dc < M;
+    double2 z = make_double2(0.0, 0.0);
+    {
+        const int j0 = it.bulk0 + tid;
+        if (j0 < it.bulk1) z = partial[j0 * ls2 + lag];
+    }
+    float2 xs[kCls], ys[kCls];
+    bool ok[kCls];
+    const int64_t lag_off = (int64_t)dr * in.lda + dc;
+#pragma unroll
+    for (int k = 0; k < kCls; ++k) {
+        const int cls = wave + 4 * k;
+        const int rho = cls - 1;
+        const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+        ok[k] = cls >= 1 && cls < ncls && col_ok && r >= rlo && r < rhi;
+        const int64_t off = ok[k] ? (int64_t)r * in.lda + c : (int64_t)rlo * in.lda;
+        xs[k] = A[off];
+        ys[k] = A[off + lag_off];
+    }
+    const double2 zc_v = wave == 0 && has_mr && col_ok ? ZC(g) : make_double2(0.0, 0.0);
+    for (int j = it.bulk0 + tid + 256; j < it.bulk1; j += 256) z = cadd(z, partial[j * ls2 + lag]);
+    // middle sum: a fixed-order butterfly in each wave, then the waves in order
+    z = wave_sum(z);
+    if (lane == 0) red[wave] = z;
+
+    // row pass
+    int glo, ghi;
+    span(lane, Kc, Cm0, Cm1, glo, ghi);   // lane = offset b
+#pragma unroll
+    for (int k = 0; k < kCls; ++k) {
+        const int cls = wave + 4 * k;
+        if (cls >= ncls) break;
+        double2 v, base = make_double2(0.0, 0.0);
+        if (cls == 0) {
+            v = zc_v;
+        } else {
+            const int rho = cls - 1;
+            const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+            if (has_mc && r >= rlo && r < rhi) base = ZR(rho);
+            v = ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
+                      : make_double2(0.0, 0.0);
+        }
+        const double2 pre = wave_scan(v);
+        const double2 sum = csub(lane_at(pre, ghi - 1), lane_at(pre, glo - 1));
+        if (lane < nc) St[lane * sst + cls] = cadd(base, sum);
+    }
+    __syncthreads();
+
+    // column pass
+    const double2 zm = has_mr ? cadd(cadd(red[0], red[1]), cadd(red[2], red[3])) : make_double2(0.0, 0.0);
+    int ra, rb;
+    span(rlo + lane, Kr, Rm0, Rm1, ra, rb);   // lane = offset a
+    const int i1 = rlo + lane;
+    for (int b = wave; b < nc; b += 4) {
+        const double2 *col = St + b * sst;
+        const double2 u = lane < nir ? col[1 + lane] : make_double2(0.0, 0.0);
+        const double2 pre = wave_scan(u);
+        const double2 sum = csub(lane_at(pre, rb - 1), lane_at(pre, ra - 1));
+        if (lane < nr) {
+            const double2 v = cadd(cadd(zm, col[0]), sum);
+            store_r(in, i1 + P * b, (i1 + dr) + P * (b + dc), v, dr == 0 && dc == 0);
+        }
+    }
+}
+
 #undef ZR
 #undef ZC
 
@@ -621,7 +771,8 @@ hipError_t prepare_rec_kernels()
                              reinterpret_cast<const void *>(&rec_main_persistent),
                              reinterpret_cast<const void *>(&rec_finalize),
                              reinterpret_cast<const void *>(&rec_finalize_tab<16, 8>),
-                             reinterpret_cast<const void *>(&rec_finalize_tab<4, 4>)};
+                             reinterpret_cast<const void *>(&rec_finalize_tab<4, 4>),
+                             reinterpret_cast<const void *>(&rec_finalize_scan)};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
             if (e != hipSuccess) return e;
@@ -660,6 +811,8 @@ hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes
         hipLaunchKernelGGL((rec_finalize_tab<16, 8>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else if (variant == kFinTableSmall)
         hipLaunchKernelGGL((rec_finalize_tab<4, 4>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else if (variant == kFinScan)
+        hipLaunchKernelGGL(rec_finalize_scan, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else
         hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
     return hipGetLastError();

@@ -290,6 +290,129 @@ def model_forward(A, P, Q, info):
     return model_finalize(A, P, Q, info, sums)
 
 
+def dpp_scan(v):
+    """The wave-scan finalize's prefix sum over 64 lanes, step by step: row
+    shifts by 1, 2 and 3 of the original values, masked row shifts by 4 (lanes
+    4-15 of each row of 16) and 8 (lanes 8-15), then the totals of row 0 into
+    rows 1 and 3 and of rows 0-1 into rows 2 and 3; lanes a step does not
+    reach add zero."""
+    v = np.asarray(v, dtype=complex)
+    i = np.arange(64)
+    s = v.copy()
+    for k in (1, 2, 3):
+        s = s + np.where(i % 16 >= k, np.roll(v, k), 0)
+    s = s + np.where(i % 16 >= 4, np.roll(s, 4), 0)
+    s = s + np.where(i % 16 >= 8, np.roll(s, 8), 0)
+    s = s + np.where(np.isin(i // 16, (1, 3)), s[(i // 16) * 16 - 1], 0)
+    s = s + np.where(i // 16 >= 2, s[31], 0)
+    return s
+
+
+def test_dpp_scan_is_a_prefix_sum():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        v = rng.integers(-1000, 1000, 64) + 1j * rng.integers(-1000, 1000, 64)
+        assert np.array_equal(dpp_scan(v), np.cumsum(v))
+
+
+def model_finalize_scan(A, P, Q, info, sums):
+    """R from the same sums as the wave-scan finalize takes them: per class
+    (the middle rows, then each individual row) a prefix sum over the
+    individual columns, read at the ends of each offset's column range; per
+    column offset a prefix sum over the individual rows, read at the ends of
+    each row offset's range; rows and columns a lag cannot use zeroed.  The
+    prefix sums are np.cumsum (test_dpp_scan_is_a_prefix_sum pins the lane
+    pattern to it; on integer inputs the order of the additions is moot)."""
+    A = np.asarray(A, dtype=np.complex128)
+    N, M = A.shape
+    Kr, Kc = N - P + 1, M - Q + 1
+    Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
+    ind_r = [r for r in range(N) if r < Rm0 or r >= Rm1]
+    ind_c = [c for c in range(M) if c < Cm0 or c >= Cm1]
+    nir = len(ind_r)
+
+    def span(x0, n, m0, m1):
+        lo = x0 if x0 < m0 else m0 + max(0, x0 - m1)
+        hi = m0 + x0 + n - m1 if x0 + n > m1 else min(m0, x0 + n)
+        return lo, hi
+
+    def at(p, i):
+        return p[i] if i >= 0 else 0
+
+    R = np.zeros((P * Q, P * Q), dtype=np.complex128)
+    for dr, dc in uc_set(P, Q):
+        rlo, rhi = max(0, -dr), N - max(0, dr)
+        zm, zr, zc = sums(dr, dc)
+        zm = zm if Rm1 > Rm0 else 0
+        nr, nc = P - abs(dr), Q - dc
+        St = np.zeros((nc, 1 + nir), complex)
+        cols = np.array(ind_c, dtype=int)
+        col_ok = cols + dc < M
+        for cls in range(1 + nir):
+            v = np.zeros(64, complex)
+            base = 0
+            if cls == 0:
+                if Rm1 > Rm0:
+                    v[:len(cols)] = [zc[c] if ok else 0 for c, ok in zip(ind_c, col_ok)]
+            else:
+                r = ind_r[cls - 1]
+                if rlo <= r < rhi:
+                    base = zr[r] if Cm1 > Cm0 else 0
+                    cc = np.where(col_ok, cols, 0)
+                    v[:len(cols)] = np.where(col_ok, A[r, cc] * np.conj(A[r + dr, cc + dc]), 0)
+            pre = np.cumsum(v)
+            for b in range(nc):
+                glo, ghi = span(b, Kc, Cm0, Cm1)
+                St[b, cls] = base + (at(pre, ghi - 1) - at(pre, glo - 1))
+        for b in range(nc):
+            u = np.zeros(64, complex)
+            u[:nir] = St[b, 1:]
+            pre = np.cumsum(u)
+            for a in range(nr):
+                ra, rb = span(rlo + a, Kr, Rm0, Rm1)
+                v = zm + St[b, 0] + (at(pre, rb - 1) - at(pre, ra - 1))
+                i1 = rlo + a
+                k1, k2 = i1 + P * b, i1 + dr + P * (b + dc)
+                K = float(Kr * Kc)
+                v = complex(v.real / K, 0.0 if k1 == k2 else v.imag / K)
+                R[k1, k2] = v
+                R[k2, k1] = v.conjugate()
+    return R
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 8, 8), (40, 33, 4, 16), (9, 9, 5, 5), (6, 7, 6, 7),
+                                   (72, 70, 12, 4), (31, 31, 16, 16), (80, 90, 32, 32)])
+def test_scan_finalize_reproduces_oracle(oracle_mod, shape):
+    """The wave-scan finalize's index ranges and prefix sums, for every plan
+    whose individual rows and columns fit one wave."""
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N + 5 * M)
+    ref = oracle_mod.forward(A, P, Q)
+    infos = [cv.plan_info(N, M, P, Q, 512, *w) for w in WIDTHS]
+    if N >= 2 * P - 1 and M >= 2 * Q - 1 and Q >= 4:
+        infos.append(cv.mfma_plan(N, M, P, Q)[0])
+    A128 = np.asarray(A, dtype=np.complex128)
+    checked = 0
+    for info in infos:
+        Rm0, Rm1, Cm0, Cm1 = info["Rm0"], info["Rm1"], info["Cm0"], info["Cm1"]
+        if info["n_ir"] > 63 or info["n_ic"] > 64:
+            continue
+
+        def sums(dr, dc):
+            Pi = np.zeros((N, M), dtype=np.complex128)
+            r0, r1 = max(0, -dr), N - max(0, dr)
+            Pi[r0:r1, :M - dc] = A128[r0:r1, :M - dc] * A128[r0 + dr:r1 + dr, dc:].conj()
+            zm = Pi[Rm0:Rm1, Cm0:Cm1].sum()
+            zr = {r: Pi[r, Cm0:Cm1].sum() for r in range(N) if r < Rm0 or r >= Rm1}
+            zc = {c: Pi[Rm0:Rm1, c].sum() for c in range(M) if c < Cm0 or c >= Cm1}
+            return zm, zr, zc
+
+        R = model_finalize_scan(A, P, Q, info, sums)
+        assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag), info
+        checked += 1
+    assert checked > 0
+
+
 @pytest.mark.parametrize("shape", [(64, 64, 8, 8), (40, 33, 4, 16), (9, 9, 5, 5), (6, 7, 6, 7),
                                    (130, 64, 3, 1), (20, 20, 1, 1), (72, 70, 12, 4)])
 def test_decomposition_reproduces_oracle(oracle_mod, shape):
