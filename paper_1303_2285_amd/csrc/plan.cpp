@@ -104,7 +104,7 @@ static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
     // corner tables (measured: 55 -> 50 us at 1024^2 / 32 x 32, 62 x 62
     // corners; tables of up to ~45 x 45, as in a batch of 4..16 windows, run
     // slower than with the table variants)
-    if (sp.n_ic <= 64 && sp.n_ir <= 63 && sp.n_ir * sp.n_ic > 2 * kFinSmallCorners) {
+    if (sp.n_ic <= 63 && sp.n_ir <= 63 && sp.n_ir * sp.n_ic > 2 * kFinSmallCorners) {
         sp.fin_variant = kFinScan;
         sp.lds_fin = (size_t)Q * ((1 + sp.n_ir) | 1) * 16;
     }

@@ -608,9 +608,9 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave, in a fixed order: three
-// shifts inside each row of 16 lanes give sums of 4, two masked shifts
-// complete the rows, two row broadcasts carry the row totals.  Lanes a shift
-// does not reach add zero.
+// shifts inside each row of 16 lanes give sums of 4, shifts by 4 and 8 (which
+// lanes near the start of a row read as zero) complete the rows, two row
+// broadcasts carry the row totals.  Lanes a step does not reach add zero.
 template <int CTRL, int RMASK, int BMASK>
 __device__ __forceinline__ double dpp_f64(double v)
 {
@@ -624,25 +624,36 @@ __device__ __forceinline__ double wave_scan(double v)
     double s = v + dpp_f64<0x111, 0xf, 0xf>(v);   // row_shr:1
     s += dpp_f64<0x112, 0xf, 0xf>(v);             // row_shr:2
     s += dpp_f64<0x113, 0xf, 0xf>(v);             // row_shr:3
-    s += dpp_f64<0x114, 0xf, 0xe>(s);             // row_shr:4, lanes 4-15 of a row
-    s += dpp_f64<0x118, 0xf, 0xc>(s);             // row_shr:8, lanes 8-15 of a row
+    s += dpp_f64<0x114, 0xf, 0xf>(s);             // row_shr:4 (lanes 0-3 of a row read zero)
+    s += dpp_f64<0x118, 0xf, 0xf>(s);             // row_shr:8 (lanes 0-7 of a row read zero)
     s += dpp_f64<0x142, 0xa, 0xf>(s);             // row_bcast:15 into rows 1 and 3
     s += dpp_f64<0x143, 0xc, 0xf>(s);             // row_bcast:31 into rows 2 and 3
     return s;
 }
 
-__device__ __forceinline__ double2 wave_scan(double2 v) { return make_double2(wave_scan(v.x), wave_scan(v.y)); }
-
-// value of P at lane i (all lanes take part), zero for i < 0
-__device__ __forceinline__ double2 lane_at(double2 p, int i)
+// exclusive prefix sum over the lanes: the sum of the lanes below this one
+__device__ __forceinline__ double2 wave_scan_excl(double2 v)
 {
-    const int j = max(i, 0);
-    const double2 v = make_double2(__shfl(p.x, j, 64), __shfl(p.y, j, 64));
-    return i < 0 ? make_double2(0.0, 0.0) : v;
+    return make_double2(wave_scan(v.x) - v.x, wave_scan(v.y) - v.y);
+}
+
+// E[hi] - E[lo] for this lane, E being the wave's values in its LDS row
+// (written just before by the same wave: a wave's LDS operations run in order)
+__device__ __forceinline__ double2 range_sum(double2 *row, double2 e, int lo, int hi)
+{
+    row[threadIdx.x & 63] = e;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double2 h = row[hi], l = row[lo];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return csub(h, l);
 }
 
 // Wave-scan variant of the finalize (256 threads, one unique combination;
-// at most 64 individual columns and 63 individual rows).  Entry (a, b) of
+// at most 63 individual columns and 63 individual rows).  Entry (a, b) of
 // the lag's segments is the sum over a box that contains the middle block:
 // the middle sum, plus for the middle rows (class 0) and every individual
 // row inside the box (classes 1..) the row's strip sum and its terms in the
@@ -650,11 +661,11 @@ __device__ __forceinline__ double2 lane_at(double2 p, int i)
 // for offset b are one contiguous range [glo, ghi) of the individual-column
 // order, the rows for offset a likewise [ra, rb) (see span), so
 //   row pass:    each wave takes classes in turn, one individual column per
-//                lane: a prefix sum over the lanes gives, for lane b, the
-//                class's sum over [glo(b), ghi(b)) from two lanes of it;
+//                lane: an exclusive prefix sum E over the lanes gives, for
+//                lane b, the class's sum over [glo(b), ghi(b)) as
+//                E[ghi] - E[glo] (read back through a row of LDS);
 //   column pass: each wave takes offsets b in turn, one individual row per
-//                lane: a prefix sum over the lanes gives, for lane a, the sum
-//                over the rows [ra(a), rb(a)).
+//                lane: likewise the sum over the rows [ra(a), rb(a)).
 // Only the classes' sums per offset live in LDS (nc x (1 + n_ir)); the corner
 // products never do.  Rows and columns a lag cannot use are zeroed before
 // the sums, so the differences of prefix sums cancel exactly what they should.
@@ -663,6 +674,7 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
     constexpr int kCls = 16;   // classes per wave at most (64 / 4 waves)
     extern __shared__ double2 St[];
     __shared__ double2 red[4];
+    __shared__ double2 xch[4][64];   // per wave: the prefix sums, read back at two lanes
     const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
     const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
     const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
@@ -734,8 +746,7 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
             v = ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
                       : make_double2(0.0, 0.0);
         }
-        const double2 pre = wave_scan(v);
-        const double2 sum = csub(lane_at(pre, ghi - 1), lane_at(pre, glo - 1));
+        const double2 sum = range_sum(xch[wave], wave_scan_excl(v), glo, ghi);
         if (lane < nc) St[lane * sst + cls] = cadd(base, sum);
     }
     __syncthreads();
@@ -748,8 +759,7 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
     for (int b = wave; b < nc; b += 4) {
         const double2 *col = St + b * sst;
         const double2 u = lane < nir ? col[1 + lane] : make_double2(0.0, 0.0);
-        const double2 pre = wave_scan(u);
-        const double2 sum = csub(lane_at(pre, rb - 1), lane_at(pre, ra - 1));
+        const double2 sum = range_sum(xch[wave], wave_scan_excl(u), ra, rb);
         if (lane < nr) {
             const double2 v = cadd(cadd(zm, col[0]), sum);
             store_r(in, i1 + P * b, (i1 + dr) + P * (b + dc), v, dr == 0 && dc == 0);

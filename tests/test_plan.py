@@ -292,10 +292,10 @@ def model_forward(A, P, Q, info):
 
 def dpp_scan(v):
     """The wave-scan finalize's prefix sum over 64 lanes, step by step: row
-    shifts by 1, 2 and 3 of the original values, masked row shifts by 4 (lanes
-    4-15 of each row of 16) and 8 (lanes 8-15), then the totals of row 0 into
-    rows 1 and 3 and of rows 0-1 into rows 2 and 3; lanes a step does not
-    reach add zero."""
+    shifts by 1, 2 and 3 of the original values, row shifts by 4 and 8 of the
+    running sums (a lane whose source lies before its row of 16 reads zero),
+    then the total of row 0 into row 1 and of row 2 into row 3, and the total
+    of rows 0-1 into rows 2 and 3; lanes a step does not reach add zero."""
     v = np.asarray(v, dtype=complex)
     i = np.arange(64)
     s = v.copy()
