@@ -446,9 +446,13 @@ static int planes_of(int prec)
     }
 }
 
-// Row stride of an LDS window: at least w, and 4 (mod 32) 4-byte elements so
-// that 16-byte reads of consecutive rows fall in different banks.
-static int pad_stride(int w) { return w + ((4 - w) % 32 + 32) % 32; }
+// Row stride of an LDS window: at least w, and 1 (mod 32) 4-byte elements.
+// The kernel reads its operands 4 bytes at a time (a lane's window column can
+// start at any element), and the 32 lanes of a half-wave take 32 different
+// rows: with an odd stride their words fall in 32 different banks.  (A stride
+// of 4 (mod 32) put them in 8 banks, a 4-way conflict that halved the speed
+// of the 16-bit forms.)
+static int pad_stride(int w) { return w + ((1 - w) % 32 + 32) % 32; }
 
 HankelPlan make_hankel_plan(int N, int M, int P, int Q, int prec, int n_cu)
 {
