@@ -77,8 +77,9 @@ typedef enum {
  * FP64 sums of the same products (each distinct product once, Sec. 3.3); they
  * differ in speed and in the order of the additions. */
 typedef enum {
-    COVEST_ENGINE_AUTO = 0,    /* matrix cores where the window suits them (at least 70%
-                                  of the 16 x 16 tiles' lags real), else vector          */
+    COVEST_ENGINE_AUTO = 0,    /* matrix cores wherever they can run, except lag blocks
+                                  of 7-8 tiles under 30% real (P = 56..64, Q = 4); in a
+                                  batch only windows whose tiles are at least 70% real */
     COVEST_ENGINE_VECTOR = 1,  /* FP64 FMA on the vector units, lags in a register ring  */
     COVEST_ENGINE_MATRIX = 2   /* FP64 MFMA: per line, a block of A times a Toeplitz band
                                   of the line; needs N >= 2P-1, M >= 2Q-1, Q >= 4 and a

@@ -169,11 +169,11 @@ int n_slots_for_device(int dev) { return 2 * cus_of_device(dev); }
 // 2 matrix cores, 0 when the requested engine cannot run the shape.
 // 2: matrix cores, 1: vector units, 0: the forced matrix engine cannot run
 // this shape.  AUTO takes the matrix cores above min_fill.
-int pick_engine(int N, int M, int P, int Q, const covest_opts &o, double min_fill = kMfmaFill)
+int pick_engine(int N, int M, int P, int Q, const covest_opts &o, bool batch = false)
 {
     if (o.engine == COVEST_ENGINE_MATRIX) return mfma_fits(N, M, P, Q) ? 2 : 0;
     if (o.engine == COVEST_ENGINE_VECTOR) return 1;
-    return (mfma_fits(N, M, P, Q, min_fill) && o.ring_cols == 0 && o.ring_rows == 0) ? 2 : 1;
+    return (mfma_preferred(N, M, P, Q, batch) && o.ring_cols == 0 && o.ring_rows == 0) ? 2 : 1;
 }
 
 ShapePlan plan_for(int N, int M, int P, int Q, int cus, int w0, int w1, int engine)
@@ -679,7 +679,7 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     // engine per problem, as for a single call
     std::vector<int> engine(count);
     for (int64_t i = 0; i < count; ++i) {
-        int e = pick_engine(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, o);
+        int e = pick_engine(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, o, true);
         if (e == 0)
             return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine does not fit %dx%d, %dx%d",
                         (long long)i, pr[i].N, pr[i].M, pr[i].P, pr[i].Q);

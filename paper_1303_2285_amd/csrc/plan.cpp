@@ -314,6 +314,15 @@ bool mfma_fits(int N, int M, int P, int Q, double min_fill)
     return (double)(2 * P - 1) * Q >= min_fill * 256.0 * mt * nt;
 }
 
+bool mfma_preferred(int N, int M, int P, int Q, bool batch)
+{
+    if (!mfma_fits(N, M, P, Q)) return false;
+    const int tiles = ((2 * P - 1 + 15) / 16) * ((Q + 15) / 16);
+    const double fill = (double)(2 * P - 1) * Q / (256.0 * tiles);
+    if (batch) return fill >= 0.7;
+    return !(fill < 0.3 && tiles >= 7);
+}
+
 ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units)
 {
     ShapePlan sp;

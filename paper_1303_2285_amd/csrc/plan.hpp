@@ -57,8 +57,16 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units 
 // The matrix-core engine needs a non-empty middle block and a lag block of at
 // most 8 tiles (one wave holds all its sums); min_fill: the least share of
 // the tiles' lags that are real (0: any).
-constexpr double kMfmaFill = 0.7;   // AUTO chooses the matrix cores above this
 bool mfma_fits(int N, int M, int P, int Q, double min_fill = 0.0);
+
+// AUTO's choice of the matrix cores for a shape the kernel can run (measured
+// on MI355X, both engines on the same inputs): a single problem almost always
+// runs faster there, down to 4 x 4 windows (the vector engine's many small
+// jobs cost more than the padding of a 16 x 16 tile), except lag blocks of 7
+// or 8 tiles that are three quarters padding (P = 56..64 with Q = 4); in a
+// batch the vector kernel's jobs fill the GPU better, and only windows whose
+// tiles are at least 70% real go to the matrix cores.
+bool mfma_preferred(int N, int M, int P, int Q, bool batch);
 
 // Ring widths worth trying for a window extent n (the first is the default).
 std::vector<int> ring_width_candidates(int n);

@@ -62,7 +62,7 @@ def test_workspace_query_errors():
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     assert "engine" in L.covest_last_error().decode()
     # the matrix-core engine: not where its kernel cannot run (Q < 4, N < 2P - 1);
-    # its own plan where it can, also for an 8 x 8 window that AUTO leaves to the vector units
+    # its own plan where it can
     assert L.covest_workspace_size(64, 64, 8, 3, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
     assert L.covest_workspace_size(64, 64, 40, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
     assert L.covest_workspace_size(64, 64, 8, 8, _opts(engine="matrix"), ctypes.byref(n)) == cv.OK
@@ -74,8 +74,13 @@ def test_workspace_query_errors():
     m = ctypes.c_size_t(0)
     assert L.covest_workspace_size(1024, 1024, 32, 32, _opts(), ctypes.byref(m)) == cv.OK
     assert m.value == max(n.value, cv.mfma_plan(1024, 1024, 32, 32)[0]["ws_bytes"])
+    # AUTO takes the matrix cores for 8 x 8 too, and covers the vector plan it
+    # falls back to for inputs too large for 32-bit offsets
     assert L.covest_workspace_size(64, 64, 8, 8, None, ctypes.byref(n)) == cv.OK
-    assert n.value == cv.plan_info(64, 64, 8, 8)["ws_bytes"]
+    assert n.value == max(cv.plan_info(64, 64, 8, 8)["ws_bytes"], cv.mfma_plan(64, 64, 8, 8)[0]["ws_bytes"])
+    # ... but not for a 64 x 4 window (8 tiles, three quarters padding)
+    assert L.covest_workspace_size(300, 300, 64, 4, None, ctypes.byref(n)) == cv.OK
+    assert n.value == cv.plan_info(300, 300, 64, 4)["ws_bytes"]
 
 
 def test_forward_argument_errors_before_device_use():

@@ -131,22 +131,26 @@ EDGE_SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("engine", ["auto", "vector"])
 @pytest.mark.parametrize("shape", EDGE_SHAPES, ids=lambda s: "x".join(map(str, s)))
-def test_edge_shapes_integer_bit_exact(cv, torch_dev, oracle_mod, shape):
+def test_edge_shapes_integer_bit_exact(cv, torch_dev, oracle_mod, shape, engine):
+    """Every shape on the engine AUTO picks (the matrix cores wherever they can
+    run) and on the vector units."""
     N, M, P, Q = shape
     A = synth.small_int(N, M, seed=N * 1000 + M * 10 + P + Q)
-    _note("edge", shape)
-    R = gpu_forward(cv, torch_dev, A, P, Q)
+    _note("edge", shape, engine)
+    R = gpu_forward(cv, torch_dev, A, P, Q, engine=engine)
     ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
     assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
 
 
+@pytest.mark.parametrize("engine", ["auto", "vector"])
 @pytest.mark.parametrize("shape", [(37, 45, 6, 9), (100, 80, 10, 10), (160, 150, 24, 31)])
-def test_edge_shapes_gaussian(cv, torch_dev, oracle_mod, shape):
+def test_edge_shapes_gaussian(cv, torch_dev, oracle_mod, shape, engine):
     N, M, P, Q = shape
     A = synth.gaussian(N, M, seed=N + M)
-    _note("gaussian", shape)
-    R = gpu_forward(cv, torch_dev, A, P, Q)
+    _note("gaussian", shape, engine)
+    R = gpu_forward(cv, torch_dev, A, P, Q, engine=engine)
     ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
     assert relF(R, ref) <= TOL_FP64
 
