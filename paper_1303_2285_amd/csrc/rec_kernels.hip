@@ -669,6 +669,7 @@ __device__ __forceinline__ double2 range_sum(double2 *row, double2 e, int lo, in
 // Only the classes' sums per offset live in LDS (nc x (1 + n_ir)); the corner
 // products never do.  Rows and columns a lag cannot use are zeroed before
 // the sums, so the differences of prefix sums cancel exactly what they should.
+template <bool INLINE>
 __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
 {
     constexpr int kCls = 16;   // classes per wave at most (64 / 4 waves)
@@ -676,7 +677,7 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
     __shared__ double2 red[4];
     __shared__ double2 xch[4][64];   // per wave: the prefix sums, read back at two lanes
     const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
-    const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
+    const Inst in = INLINE ? fa.inst_inline : fa.insts[it.inst];
     const int P = in.P, N = in.N, M = in.M, Kr = in.Kr, Kc = in.Kc;
     const int dr = it.dr, dc = it.dc;
     const int lag = (dr + P - 1) * in.Q + dc;
@@ -724,6 +725,13 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
         ys[k] = A[off + lag_off];
     }
     const double2 zc_v = wave == 0 && has_mr && col_ok ? ZC(g) : make_double2(0.0, 0.0);
+    // the row strips of this wave's classes: lane k holds class wave + 4k's
+    double2 zr_l = make_double2(0.0, 0.0);
+    {
+        const int cls = wave + 4 * lane, rho = cls - 1;
+        const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
+        if (lane < kCls && cls >= 1 && cls < ncls && has_mc && r >= rlo && r < rhi) zr_l = ZR(rho);
+    }
     for (int j = it.bulk0 + tid + 256; j < it.bulk1; j += 256) z = cadd(z, partial[j * ls2 + lag]);
     // middle sum: a fixed-order butterfly in each wave, then the waves in order
     z = wave_sum(z);
@@ -736,16 +744,15 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
     for (int k = 0; k < kCls; ++k) {
         const int cls = wave + 4 * k;
         if (cls >= ncls) break;
-        double2 v, base = make_double2(0.0, 0.0);
-        if (cls == 0) {
-            v = zc_v;
-        } else {
-            const int rho = cls - 1;
-            const int r = rho < Rm0 ? rho : Rm1 + (rho - Rm0);
-            if (has_mc && r >= rlo && r < rhi) base = ZR(rho);
-            v = ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
-                      : make_double2(0.0, 0.0);
-        }
+        const double2 v = cls == 0 ? zc_v
+                          : ok[k] ? cprod(make_double2(xs[k].x, xs[k].y), make_double2(ys[k].x, ys[k].y))
+                                  : make_double2(0.0, 0.0);
+        // lane k's row strip, read into scalar registers (zero for class 0)
+        const double2 base = make_double2(
+            __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(zr_l.x), k),
+                             __builtin_amdgcn_readlane(__double2loint(zr_l.x), k)),
+            __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(zr_l.y), k),
+                             __builtin_amdgcn_readlane(__double2loint(zr_l.y), k)));
         const double2 sum = range_sum(xch[wave], wave_scan_excl(v), glo, ghi);
         if (lane < nc) St[lane * sst + cls] = cadd(base, sum);
     }
@@ -782,7 +789,8 @@ hipError_t prepare_rec_kernels()
                              reinterpret_cast<const void *>(&rec_finalize),
                              reinterpret_cast<const void *>(&rec_finalize_tab<16, 8>),
                              reinterpret_cast<const void *>(&rec_finalize_tab<4, 4>),
-                             reinterpret_cast<const void *>(&rec_finalize_scan)};
+                             reinterpret_cast<const void *>(&rec_finalize_scan<true>),
+                             reinterpret_cast<const void *>(&rec_finalize_scan<false>)};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
             if (e != hipSuccess) return e;
@@ -821,8 +829,10 @@ hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes
         hipLaunchKernelGGL((rec_finalize_tab<16, 8>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else if (variant == kFinTableSmall)
         hipLaunchKernelGGL((rec_finalize_tab<4, 4>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else if (variant == kFinScan && fa.use_inline)
+        hipLaunchKernelGGL(rec_finalize_scan<true>, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else if (variant == kFinScan)
-        hipLaunchKernelGGL(rec_finalize_scan, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+        hipLaunchKernelGGL(rec_finalize_scan<false>, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else
         hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
     return hipGetLastError();
