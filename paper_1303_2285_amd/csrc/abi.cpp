@@ -529,9 +529,9 @@ void free_plan(covest_plan *p)
 }
 
 // ------------------------------------------------------------- autotuner --
-// Ring widths (tile shapes of the main kernel) per (P, Q) class, chosen by
-// timing the main kernel on the largest problem of the class.  Results are
-// kept for the process and, when COVEST_TUNE_CACHE names a file, in that file
+// Ring widths (tile shapes of the vector kernel) per (P, Q) class, chosen by
+// timing the class's problems as the batch runs them.  Results are kept for
+// the process and, when COVEST_TUNE_CACHE names a file, in that file
 // ("P Q W0 W1" per line).  COVEST_TUNE=0 keeps the default widths.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
@@ -576,96 +576,185 @@ bool tuning_enabled()
     return !(s && s[0] == '0');
 }
 
-// Time rec_main for one problem and plan (events on a private stream).
-int time_main(const ShapePlan &sp, const covest_problem &p, const covest_opts &o, void *ws, void *R,
-              hipStream_t s, float *best_ms)
+// Time the vector kernel on every problem of one (P, Q) class with ring
+// widths (w0, w1), as the batch runs them: each problem split into jobs in
+// proportion to its cost, all jobs longest first in one persistent launch
+// (events on a private stream, best of three after a warm-up).  The kernel
+// writes only workspace sums, so no output is touched.
+using Widths = std::map<std::pair<int, int>, std::pair<int, int>>;
+
+int time_class(const covest_problem *pr, const std::vector<int64_t> &members, const covest_opts &o,
+               int resident, const Widths &widths, size_t lds_cap, hipStream_t s, float *best_ms)
 {
+    auto wfor = [&](const covest_problem &p) {
+        auto it = widths.find({(int)p.P, (int)p.Q});
+        return it == widths.end() ? std::make_pair(0, 0) : it->second;
+    };
+    std::vector<double> cost(members.size(), 0.0);
+    double total = 0.0;
+    for (size_t t = 0; t < members.size(); ++t) {
+        const covest_problem &p = pr[members[t]];
+        const auto w = wfor(p);
+        for (double c : make_shape_plan(p.N, p.M, p.P, p.Q, 1, w.first, w.second).job_cost) cost[t] += c;
+        total += cost[t];
+    }
+    const double target = std::max(1.0, total / (3.0 * resident));
+    std::vector<ShapePlan> plans;
+    size_t ws_off = 0, lds = 0;
+    std::vector<size_t> ws_base;
+    for (size_t t = 0; t < members.size(); ++t) {
+        const covest_problem &p = pr[members[t]];
+        const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(resident, std::llround(cost[t] / target)));
+        const auto w = wfor(p);
+        plans.push_back(make_shape_plan(p.N, p.M, p.P, p.Q, slots, w.first, w.second));
+        ws_base.push_back(ws_off);
+        ws_off += (plans.back().ws_bytes + 255) / 256 * 256;
+        lds = std::max(lds, plans.back().lds_main);
+    }
+    if (lds > lds_cap) {   // would lower the occupancy of the whole batch's launch
+        *best_ms = 1e30f;
+        return COVEST_OK;
+    }
+    lds = lds_cap;   // the batch launches with the largest LDS of any of its problems
+    void *ws = nullptr;
+    HIP_TRY(hipMalloc(&ws, std::max<size_t>(ws_off, 256)));
+    std::vector<Job> jobs;
+    std::vector<double> jcost;
+    std::vector<LagGroup> groups;
+    std::vector<Inst> insts;
+    for (size_t t = 0; t < plans.size(); ++t) {
+        const ShapePlan &sp = plans[t];
+        const covest_problem &p = pr[members[t]];
+        const int goff = (int)groups.size();
+        groups.insert(groups.end(), sp.groups.begin(), sp.groups.end());
+        for (size_t j = 0; j < sp.jobs.size(); ++j) {
+            Job jb = sp.jobs[j];
+            jb.inst = (int)t;
+            jb.group += goff;
+            jobs.push_back(jb);
+            jcost.push_back(sp.job_cost[j]);
+        }
+        insts.push_back(make_inst(sp, p.A, p.M, p.R, (int64_t)p.P * p.Q, static_cast<char *>(ws) + ws_base[t], o));
+    }
+    std::vector<size_t> order(jobs.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return jcost[a] > jcost[b]; });
+    std::vector<Job> sorted;
+    for (size_t j : order) sorted.push_back(jobs[j]);
     Job *dj = nullptr;
     LagGroup *dg = nullptr;
-    HIP_TRY(upload(&dj, sp.jobs));
-    HIP_TRY(upload(&dg, sp.groups));
-    MainArgs ma{};
-    ma.jobs = dj;
-    ma.groups = dg;
-    ma.n_jobs = (int)sp.jobs.size();
-    ma.xcd_remap = 1;
-    ma.use_inline = 1;
-    ma.inst_inline = make_inst(sp, p.A, p.M, R, (int64_t)p.P * p.Q, ws, o);
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
+    Inst *di = nullptr;
+    unsigned int *counter = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = upload(&dj, sorted);
+    if (e == hipSuccess) e = upload(&dg, groups);
+    if (e == hipSuccess) e = upload(&di, insts);
+    if (e == hipSuccess) e = hipMalloc(&counter, 256);
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
     float best = 1e30f;
-    hipError_t e = hipSuccess;
-    for (int rep = 0; rep < 4 && e == hipSuccess && ma.n_jobs > 0; ++rep) {
-        (void)hipEventRecord(a, s);
-        e = launch_rec_main(ma, ma.n_jobs, sp.lds_main, s);
-        (void)hipEventRecord(b, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float ms = 0.f;
-        if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) best = std::min(best, ms);
+    if (e == hipSuccess && !sorted.empty()) {
+        MainArgs ma{};
+        ma.jobs = dj;
+        ma.groups = dg;
+        ma.insts = di;
+        ma.n_jobs = (int)sorted.size();
+        ma.use_inline = 0;
+        const int grid = std::max(1, std::min(resident, ma.n_jobs));
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+            (void)hipEventRecord(a, s);
+            e = launch_rec_persistent(ma, counter, grid, lds, s);
+            (void)hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) best = std::min(best, ms);
+        }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    (void)hipFree(dj);
-    (void)hipFree(dg);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    for (void *ptr : {(void *)dj, (void *)dg, (void *)di, (void *)counter, ws})
+        if (ptr) (void)hipFree(ptr);
     if (e != hipSuccess) return fail(COVEST_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
     *best_ms = best;
     return COVEST_OK;
 }
 
-// Widths for every (P, Q) class of the batch.
+// Widths for every (P, Q) class of the batch that runs on the vector engine.
+// Per class, a coordinate search (the column width, then the row width) over
+// ring_width_candidates, timing the class's problems as the batch runs them;
+// a candidate needs no more LDS than the batch's default plans (all vector
+// jobs share one launch: a wider tile for one class would lower the
+// occupancy of every other) and must be at least 3% faster.  A class's
+// choice is then kept only if the launch of the whole batch's vector jobs
+// gets at least 2% faster with it: the classes' jobs run side by side, and
+// a choice that wins alone can lose in the mix (measured: choices made alone
+// made the 512-problem batch 8% slower than the defaults).
 int autotune(const covest_problem *pr, int64_t count, const std::vector<int> &engine, const covest_opts &o,
              int resident, std::map<std::pair<int, int>, std::pair<int, int>> *out)
 {
-    std::map<std::pair<int, int>, int64_t> rep;   // class -> representative problem
-    for (int64_t i = 0; i < count; ++i) {
-        if (engine[i] != 1) continue;   // only the vector engine has widths to tune
-        const auto key = std::make_pair((int)pr[i].P, (int)pr[i].Q);
-        auto it = rep.find(key);
-        if (it == rep.end() || (int64_t)pr[i].N * pr[i].M > (int64_t)pr[it->second].N * pr[it->second].M)
-            rep[key] = i;
-    }
+    std::map<std::pair<int, int>, std::vector<int64_t>> classes;
+    for (int64_t i = 0; i < count; ++i)
+        if (engine[i] == 1) classes[{(int)pr[i].P, (int)pr[i].Q}].push_back(i);   // vector engine only
+    size_t lds_cap = 0;
+    for (auto &kv : classes)
+        for (int64_t i : kv.second)
+            lds_cap = std::max(lds_cap, make_shape_plan(pr[i].N, pr[i].M, pr[i].P, pr[i].Q, 1).lds_main);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     hipStream_t s = nullptr;
-    for (auto &kv : rep) {
+    std::vector<int64_t> all;   // every vector-engine problem of the batch
+    for (auto &kv : classes) all.insert(all.end(), kv.second.begin(), kv.second.end());
+    Widths chosen, pending;
+    for (auto &kv : classes) {
         const int P = kv.first.first, Q = kv.first.second;
         auto hit = g_tune.find(kv.first);
         if (hit != g_tune.end()) {
-            (*out)[kv.first] = hit->second;
+            chosen[kv.first] = hit->second;
             continue;
         }
-        if (!tuning_enabled()) continue;
-        if (!s) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        const covest_problem &p = pr[kv.second];
-        const std::vector<int> c0 = ring_width_candidates(Q), c1 = ring_width_candidates(P);
-        size_t ws_max = 0;
-        for (int w0 : c0)
-            for (int w1 : c1) ws_max = std::max(ws_max, make_shape_plan(p.N, p.M, P, Q, resident, w0, w1).ws_bytes);
-        void *ws = nullptr, *R = nullptr;
-        HIP_TRY(hipMalloc(&ws, std::max<size_t>(ws_max, 256)));
-        HIP_TRY(hipMalloc(&R, (size_t)P * Q * P * Q * 16));
-        // coordinate search: the column width first, then the row width
-        int b0 = c0[0], b1 = c1[0];
-        float best = 1e30f;
-        for (int w0 : c0) {
-            float ms;
-            int st = time_main(make_shape_plan(p.N, p.M, P, Q, resident, w0, b1), p, o, ws, R, s, &ms);
-            if (st != COVEST_OK) { (void)hipFree(ws); (void)hipFree(R); (void)hipStreamDestroy(s); return st; }
-            if (ms < best) { best = ms; b0 = w0; }
-        }
-        for (size_t k = 1; k < c1.size(); ++k) {
-            float ms;
-            int st = time_main(make_shape_plan(p.N, p.M, P, Q, resident, b0, c1[k]), p, o, ws, R, s, &ms);
-            if (st != COVEST_OK) { (void)hipFree(ws); (void)hipFree(R); (void)hipStreamDestroy(s); return st; }
-            if (ms < best) { best = ms; b1 = c1[k]; }
-        }
-        (void)hipFree(ws);
-        (void)hipFree(R);
-        tune_store_locked(P, Q, b0, b1);
-        (*out)[kv.first] = {b0, b1};
+        chosen[kv.first] = {ring_width_candidates(Q)[0], ring_width_candidates(P)[0]};
+        if (tuning_enabled()) pending[kv.first] = chosen[kv.first];
     }
-    if (s) (void)hipStreamDestroy(s);
+    int st = COVEST_OK;
+    if (!pending.empty()) {
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        // the whole batch's vector launch with the current choices
+        float whole;
+        st = time_class(pr, all, o, resident, chosen, lds_cap, s, &whole);
+        for (auto &kv : pending) {
+            if (st != COVEST_OK) break;
+            const int P = kv.first.first, Q = kv.first.second;
+            const std::vector<int> c0 = ring_width_candidates(Q), c1 = ring_width_candidates(P);
+            int b0 = c0[0], b1 = c1[0];
+            float best;
+            st = time_class(pr, classes[kv.first], o, resident, {{kv.first, {b0, b1}}}, lds_cap, s, &best);
+            auto try_widths = [&](int w0, int w1) {
+                float ms;
+                st = time_class(pr, classes[kv.first], o, resident, {{kv.first, {w0, w1}}}, lds_cap, s, &ms);
+                if (st == COVEST_OK && ms < 0.97f * best) {
+                    best = ms;
+                    b0 = w0;
+                    b1 = w1;
+                }
+            };
+            for (size_t k = 1; k < c0.size() && st == COVEST_OK; ++k) try_widths(c0[k], b1);
+            for (size_t k = 1; k < c1.size() && st == COVEST_OK; ++k) try_widths(b0, c1[k]);
+            if (st == COVEST_OK && std::make_pair(b0, b1) != chosen[kv.first]) {
+                Widths trial = chosen;
+                trial[kv.first] = {b0, b1};
+                float ms;
+                st = time_class(pr, all, o, resident, trial, lds_cap, s, &ms);
+                if (st == COVEST_OK && ms < 0.98f * whole) {
+                    whole = ms;
+                    chosen = trial;
+                }
+            }
+            if (st == COVEST_OK) tune_store_locked(P, Q, chosen[kv.first].first, chosen[kv.first].second);
+        }
+        (void)hipStreamDestroy(s);
+    }
+    if (st != COVEST_OK) return st;
+    for (auto &kv : chosen) (*out)[kv.first] = kv.second;
     return COVEST_OK;
 }
 
