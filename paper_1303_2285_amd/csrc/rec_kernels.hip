@@ -14,9 +14,13 @@
 //               per lag), row-strip jobs (middle columns, one sum per
 //               individual row) and column-strip jobs (middle rows, one sum per
 //               individual column; walked on the transposed tile).
-// rec_finalize  one wave per unique combination: adds the corner products,
-//               slides the box along the segment (FP64 carries), divides by K
-//               and writes the segment entries (upper triangle and mirror).
+// rec_finalize  the finalize, one unique combination at a time: adds the
+//               corner products, slides the box along the segment (FP64
+//               carries), divides by K and writes the segment entries (upper
+//               triangle and mirror).  Variants: rec_finalize (one wave per
+//               combination, any size), rec_finalize_tab (a workgroup with the
+//               corner table in LDS) and rec_finalize_scan (a workgroup, wave
+//               prefix sums instead of slides, for large corner tables).
 //
 // Arithmetic: complex64 inputs are widened to FP64 once, when a tile is staged
 // in LDS.  A product of two floats is exact in FP64, so every sum is an FP64
