@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
     ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, aperture and adjoint workloads")
     ap.add_argument("--no-vector", action="store_true",
                     help="skip the comparison run of the recurrence on the vector engine")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -166,8 +166,9 @@ import numpy as np  # noqa: E402
 
 
 def extra_workloads(covest, synth, torch, dev):
-    """The batch workload (512 uneven problems in one graph replay) and the
-    differentiation workload (512 x 512, 16 x 16: forward + adjoint)."""
+    """The batch workload (512 uneven problems in one graph replay), the
+    imaging workload (R of every aperture of one image, one graph replay) and
+    the differentiation workload (512 x 512, 16 x 16: forward + adjoint)."""
     out = {}
     batch = synth.batch(512, seed=4)
     As = [torch.from_numpy(A).to(dev) for (A, P, Q) in batch]
@@ -191,6 +192,31 @@ def extra_workloads(covest, synth, torch, dev):
     print(f"[bench] batched: {dt * 1e3:.3f} ms per 512 matrices", file=sys.stderr, flush=True)
     plan.close()
     del As
+    H, W_img, ar, ac, sr, sc, nr, nc, Pa, Qa, seed = synth.APERTURE_GRIDS["sar_1600"]
+    img = torch.from_numpy(synth.aperture_image(H, W_img, seed)).to(dev)
+    t0 = time.perf_counter()
+    plan = covest.AperturePlan(img, ar, ac, sr, sc, nr, nc, Pa, Qa)
+    t_plan = time.perf_counter() - t0
+    for _ in range(2):
+        plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    n_ap = nr * nc
+    um = n_ap * covest.counts(ar, ac, Pa, Qa)["um"]
+    out["apertures"] = {"workload": f"{H}x{W_img} image of 8 2-D exponentials + noise (seed {seed}), "
+                                    f"{nr}x{nc} apertures of {ar}x{ac} at step {sr}, {Pa}x{Qa} window, "
+                                    f"{n_ap} R of {Pa * Qa}x{Pa * Qa} complex128, one graph replay",
+                        "ms_per_image": dt * 1e3, "matrices_per_s": n_ap / dt,
+                        "gflops_algorithmic": 8.0 * um / dt / 1e9,
+                        "fp64_roof_ms": 8.0 * um / (FP64_PEAK_TFLOPS * 1e12) * 1e3,
+                        "r_write_gb_s": n_ap * (Pa * Qa) ** 2 * 16 / dt / 1e9, "plan_s": t_plan}
+    print(f"[bench] apertures: {dt * 1e3:.3f} ms per image ({n_ap} matrices)", file=sys.stderr, flush=True)
+    plan.close()
+    del img
     A, W, At = synth.adjoint_inputs()
     Ad = torch.from_numpy(A).to(dev)
     G = torch.from_numpy(W.astype(np.complex64)).to(dev)

@@ -168,6 +168,45 @@ int covest_plan_batched_create(covest_plan **out, const covest_problem *problems
 int covest_forward_batched(covest_plan *plan, hipStream_t stream);
 int covest_plan_destroy(covest_plan *plan);
 
+/* One problem of a batch over strided views: A[n*lda + m] (lda >= M elements)
+ * and R[k1*ldr + k2] (ldr >= PQ elements), so that the problems of a batch can
+ * be windows into one larger array.  Device pointers, as above. */
+typedef struct {
+    const void *A;
+    void *R;
+    int64_t lda, ldr;
+    int32_t N, M, P, Q;
+} covest_problem_ex;
+
+/* As covest_plan_batched_create, for strided problems (the same checks, and
+ * COVEST_ERR_INVALID_ARG for lda < M or ldr < PQ). */
+int covest_plan_batched_create_ex(covest_plan **out, const covest_problem_ex *problems, int64_t count,
+                                  const covest_opts *opts, hipStream_t stream);
+
+/* The apertures of one image (Sec. 2.3: minimum-variance SAR imaging divides
+ * an image into overlapping apertures and needs the estimated covariance
+ * matrix of every one of them, with the same P x Q window).  Aperture (a, b),
+ * 0 <= a < n_rows, 0 <= b < n_cols, is the ap_rows x ap_cols block of the
+ * image whose first element is image[(a*row_step)*ld + b*col_step]; it is one
+ * problem of a batched plan (N = ap_rows, M = ap_cols, lda = ld).  Its R is
+ * the PQ x PQ matrix at R + (a*n_cols + b) * PQ*PQ elements (contiguous,
+ * ldr = PQ; complex128 or complex64 as opts->prec says).
+ * Errors: COVEST_ERR_INVALID_ARG for null pointers, ld < W, a step below 1 or
+ * a count below 1; COVEST_ERR_SHAPE when an aperture leaves the image
+ * ((n_rows-1)*row_step + ap_rows > H, likewise for columns), for a window
+ * larger than an aperture, or for more than 2^31 - 1 apertures; otherwise as
+ * covest_plan_batched_create.  The image and R must stay valid while the
+ * plan is used; covest_forward_batched recomputes every R from the image. */
+typedef struct {
+    const void *image;
+    int64_t ld, H, W;
+    int64_t ap_rows, ap_cols;
+    int64_t row_step, col_step;
+    int64_t n_rows, n_cols;
+} covest_aperture_grid;
+int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *grid, int64_t P, int64_t Q,
+                                 void *R, const covest_opts *opts, hipStream_t stream);
+
 /* Kernel timing for benchmarks: while enabled, every kernel the library
  * launches is bracketed by HIP events on its stream and its duration is added
  * to a per-kernel total.  covest_timing_read copies up to `cap` records (name,

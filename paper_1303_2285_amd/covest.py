@@ -7,6 +7,7 @@ built library is missing the import fails loudly; there is no fallback path.
     R = covest_forward(A, P, Q)                 # complex128 R on A's device
     dA = covest_backward(A, dR, P, Q)
     plan = BatchedPlan([(A0, P0, Q0), ...]); plan.run(); plan.outputs
+    plan = AperturePlan(image, 100, 100, 62, 62, 25, 25, 10, 10); plan.run()
 """
 from __future__ import annotations
 
@@ -54,6 +55,18 @@ class covest_problem(ctypes.Structure):
                 ("M", ctypes.c_int32), ("P", ctypes.c_int32), ("Q", ctypes.c_int32)]
 
 
+class covest_problem_ex(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("R", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("ldr", ctypes.c_int64), ("N", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("Q", ctypes.c_int32)]
+
+
+class covest_aperture_grid(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p)] + \
+               [(n, ctypes.c_int64) for n in ("ld", "H", "W", "ap_rows", "ap_cols", "row_step", "col_step",
+                                              "n_rows", "n_cols")]
+
+
 class covest_timing_record(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -92,6 +105,10 @@ SIGNATURES = {
                                _vp, ctypes.c_size_t, _vp]),
     "covest_plan_batched_create": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_problem), _i64,
                                           ctypes.POINTER(covest_opts), _vp]),
+    "covest_plan_batched_create_ex": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_problem_ex), _i64,
+                                             ctypes.POINTER(covest_opts), _vp]),
+    "covest_plan_apertures_create": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_aperture_grid), _i64,
+                                            _i64, _vp, ctypes.POINTER(covest_opts), _vp]),
     "covest_forward_batched": (_int, [_vp, _vp]),
     "covest_plan_destroy": (_int, [_vp]),
     "covest_timing_enable": (_int, [_int]),
@@ -266,32 +283,8 @@ class _Problem:
     Q: int
 
 
-class BatchedPlan:
-    """Many (A, P, Q) problems computed by one graph launch (covest_forward_batched)."""
-
-    def __init__(self, problems, precision="fp64", fill="full", normalize=True, ring_cols=0,
-                 ring_rows=0, engine="auto"):
-        torch = _torch()
-        self._problems = [_Problem(A, int(P), int(Q)) for (A, P, Q) in problems]
-        o = make_opts("recurrence", precision, fill, normalize, ring_cols, ring_rows, engine)
-        rdtype = torch.complex128 if o.prec == 0 else torch.complex64
-        arr = (covest_problem * len(self._problems))()
-        self.outputs = []
-        for i, pr in enumerate(self._problems):
-            _check_input(pr.A)
-            N, M = pr.A.shape
-            if pr.A.stride(0) != M:
-                raise ValueError("batched inputs must be contiguous")
-            R = torch.empty((pr.P * pr.Q, pr.P * pr.Q), dtype=rdtype, device=pr.A.device)
-            if fill == "upper":
-                R.zero_()
-            self.outputs.append(R)
-            arr[i] = covest_problem(pr.A.data_ptr(), R.data_ptr(), N, M, pr.P, pr.Q)
-        self._handle = ctypes.c_void_p(0)
-        dev = self._problems[0].A.device if self._problems else torch.device("cuda")
-        self._device = dev
-        _check(lib().covest_plan_batched_create(ctypes.byref(self._handle), arr, len(self._problems),
-                                                ctypes.byref(o), _stream_handle(dev)))
+class _PlanHandle:
+    """Owns a covest_plan: run() replays its graph on the current stream."""
 
     def run(self):
         _check(lib().covest_forward_batched(self._handle, _stream_handle(self._device)))
@@ -307,6 +300,63 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+class BatchedPlan(_PlanHandle):
+    """Many (A, P, Q) problems computed by one graph launch (covest_forward_batched).
+
+    Each A may be a strided view (unit column stride, any row stride), e.g. a
+    block of a larger image."""
+
+    def __init__(self, problems, precision="fp64", fill="full", normalize=True, ring_cols=0,
+                 ring_rows=0, engine="auto"):
+        torch = _torch()
+        self._handle = ctypes.c_void_p(0)
+        self._problems = [_Problem(A, int(P), int(Q)) for (A, P, Q) in problems]
+        o = make_opts("recurrence", precision, fill, normalize, ring_cols, ring_rows, engine)
+        rdtype = torch.complex128 if o.prec == 0 else torch.complex64
+        arr = (covest_problem_ex * len(self._problems))()
+        self.outputs = []
+        for i, pr in enumerate(self._problems):
+            _check_input(pr.A)
+            N, M = pr.A.shape
+            R = torch.empty((pr.P * pr.Q, pr.P * pr.Q), dtype=rdtype, device=pr.A.device)
+            if fill == "upper":
+                R.zero_()
+            self.outputs.append(R)
+            arr[i] = covest_problem_ex(pr.A.data_ptr(), R.data_ptr(), pr.A.stride(0), pr.P * pr.Q,
+                                       N, M, pr.P, pr.Q)
+        dev = self._problems[0].A.device if self._problems else torch.device("cuda")
+        self._device = dev
+        _check(lib().covest_plan_batched_create_ex(ctypes.byref(self._handle), arr, len(self._problems),
+                                                   ctypes.byref(o), _stream_handle(dev)))
+
+
+class AperturePlan(_PlanHandle):
+    """R of every aperture of one image (covest_plan_apertures_create).
+
+    Aperture (a, b) is image[a*row_step : a*row_step + ap_rows,
+    b*col_step : b*col_step + ap_cols]; `outputs` is one tensor of shape
+    (n_rows, n_cols, PQ, PQ), complex128 for precision "fp64"."""
+
+    def __init__(self, image, ap_rows, ap_cols, row_step, col_step, n_rows, n_cols, P, Q,
+                 precision="fp64", fill="full", normalize=True, engine="auto"):
+        torch = _torch()
+        self._handle = ctypes.c_void_p(0)
+        _check_input(image)
+        o = make_opts("recurrence", precision, fill, normalize, 0, 0, engine)
+        rdtype = torch.complex128 if o.prec == 0 else torch.complex64
+        PQ = int(P) * int(Q)
+        alloc = torch.zeros if fill == "upper" else torch.empty
+        self.outputs = alloc((int(n_rows), int(n_cols), PQ, PQ), dtype=rdtype, device=image.device)
+        self.image = image
+        self._device = image.device
+        g = covest_aperture_grid(image.data_ptr(), image.stride(0), image.shape[0], image.shape[1],
+                                 int(ap_rows), int(ap_cols), int(row_step), int(col_step), int(n_rows),
+                                 int(n_cols))
+        _check(lib().covest_plan_apertures_create(ctypes.byref(self._handle), ctypes.byref(g), int(P), int(Q),
+                                                  ctypes.c_void_p(self.outputs.data_ptr()), ctypes.byref(o),
+                                                  _stream_handle(image.device)))
 
 
 def covest_forward_batched(plan: BatchedPlan):

@@ -483,7 +483,8 @@ AdjGeom adj_geometry(int N, int M, int P, int Q)
 
 // -------------------------------------------------------------- batches ----
 // A batched plan: one work list for every problem (longest job first), the
-// persistent main kernel, both finalize variants, all captured in one graph.
+// persistent main kernel, one matrix-core launch per lag-block shape and one
+// finalize launch per finalize variant, all captured in one graph.
 struct covest_plan {
     int device = 0;
     covest_opts opts{};
@@ -583,17 +584,17 @@ bool tuning_enabled()
 // writes only workspace sums, so no output is touched.
 using Widths = std::map<std::pair<int, int>, std::pair<int, int>>;
 
-int time_class(const covest_problem *pr, const std::vector<int64_t> &members, const covest_opts &o,
+int time_class(const covest_problem_ex *pr, const std::vector<int64_t> &members, const covest_opts &o,
                int resident, const Widths &widths, size_t lds_cap, hipStream_t s, float *best_ms)
 {
-    auto wfor = [&](const covest_problem &p) {
+    auto wfor = [&](const covest_problem_ex &p) {
         auto it = widths.find({(int)p.P, (int)p.Q});
         return it == widths.end() ? std::make_pair(0, 0) : it->second;
     };
     std::vector<double> cost(members.size(), 0.0);
     double total = 0.0;
     for (size_t t = 0; t < members.size(); ++t) {
-        const covest_problem &p = pr[members[t]];
+        const covest_problem_ex &p = pr[members[t]];
         const auto w = wfor(p);
         for (double c : make_shape_plan(p.N, p.M, p.P, p.Q, 1, w.first, w.second).job_cost) cost[t] += c;
         total += cost[t];
@@ -603,7 +604,7 @@ int time_class(const covest_problem *pr, const std::vector<int64_t> &members, co
     size_t ws_off = 0, lds = 0;
     std::vector<size_t> ws_base;
     for (size_t t = 0; t < members.size(); ++t) {
-        const covest_problem &p = pr[members[t]];
+        const covest_problem_ex &p = pr[members[t]];
         const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(resident, std::llround(cost[t] / target)));
         const auto w = wfor(p);
         plans.push_back(make_shape_plan(p.N, p.M, p.P, p.Q, slots, w.first, w.second));
@@ -624,7 +625,7 @@ int time_class(const covest_problem *pr, const std::vector<int64_t> &members, co
     std::vector<Inst> insts;
     for (size_t t = 0; t < plans.size(); ++t) {
         const ShapePlan &sp = plans[t];
-        const covest_problem &p = pr[members[t]];
+        const covest_problem_ex &p = pr[members[t]];
         const int goff = (int)groups.size();
         groups.insert(groups.end(), sp.groups.begin(), sp.groups.end());
         for (size_t j = 0; j < sp.jobs.size(); ++j) {
@@ -634,7 +635,7 @@ int time_class(const covest_problem *pr, const std::vector<int64_t> &members, co
             jobs.push_back(jb);
             jcost.push_back(sp.job_cost[j]);
         }
-        insts.push_back(make_inst(sp, p.A, p.M, p.R, (int64_t)p.P * p.Q, static_cast<char *>(ws) + ws_base[t], o));
+        insts.push_back(make_inst(sp, p.A, p.lda, p.R, p.ldr, static_cast<char *>(ws) + ws_base[t], o));
     }
     std::vector<size_t> order(jobs.size());
     for (size_t j = 0; j < order.size(); ++j) order[j] = j;
@@ -689,7 +690,7 @@ int time_class(const covest_problem *pr, const std::vector<int64_t> &members, co
 // gets at least 2% faster with it: the classes' jobs run side by side, and
 // a choice that wins alone can lose in the mix (measured: choices made alone
 // made the 512-problem batch 8% slower than the defaults).
-int autotune(const covest_problem *pr, int64_t count, const std::vector<int> &engine, const covest_opts &o,
+int autotune(const covest_problem_ex *pr, int64_t count, const std::vector<int> &engine, const covest_opts &o,
              int resident, std::map<std::pair<int, int>, std::pair<int, int>> *out)
 {
     std::map<std::pair<int, int>, std::vector<int64_t>> classes;
@@ -758,7 +759,7 @@ int autotune(const covest_problem *pr, int64_t count, const std::vector<int> &en
     return COVEST_OK;
 }
 
-int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, const covest_opts &o,
+int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count, const covest_opts &o,
                   hipStream_t stream)
 {
     HIP_TRY(hipGetDevice(&plan->device));
@@ -772,9 +773,9 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
         if (e == 0)
             return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine does not fit %dx%d, %dx%d",
                         (long long)i, pr[i].N, pr[i].M, pr[i].P, pr[i].Q);
-        if (e == 2 && (int64_t)pr[i].N * pr[i].M + pr[i].M >= ((int64_t)1 << 31)) {
+        if (e == 2 && (int64_t)pr[i].N * pr[i].lda + pr[i].M >= ((int64_t)1 << 31)) {
             if (o.engine == COVEST_ENGINE_MATRIX)
-                return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine needs N * M < 2^31",
+                return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: the matrix-core engine needs N * lda < 2^31",
                             (long long)i);
             e = 1;
         }
@@ -864,7 +865,7 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
         }
         if (engine[i] != 2) plan->lds_main = std::max(plan->lds_main, sp.lds_main);
         plan->lds_fin[var] = std::max(plan->lds_fin[var], sp.lds_fin);
-        insts[i] = make_inst(sp, pr[i].A, pr[i].M, pr[i].R, (int64_t)pr[i].P * pr[i].Q,
+        insts[i] = make_inst(sp, pr[i].A, pr[i].lda, pr[i].R, pr[i].ldr,
                              static_cast<char *>(plan->d_ws) + ws_base[i], o);
     }
     // longest job first (stable, so equal jobs keep their spatial order)
@@ -946,6 +947,41 @@ int build_batched(covest_plan *plan, const covest_problem *pr, int64_t count, co
     plan->graph = g;
     HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
     return COVEST_OK;
+}
+
+// The checks and plan construction shared by the batched entry points.
+int create_batched(covest_plan **out, const covest_problem_ex *problems, int64_t count, const covest_opts *opts,
+                   hipStream_t stream)
+{
+    covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    if (o.form == COVEST_FORM_HANKEL_MFMA)
+        return fail(COVEST_ERR_UNSUPPORTED, "batched plans use the recurrence form");
+    if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
+        return fail(COVEST_ERR_UNSUPPORTED, "batched plans compute in FP64 (prec FP64 or FP32 output)");
+    for (int64_t i = 0; i < count; ++i) {
+        const covest_problem_ex &p = problems[i];
+        st = check_shape(p.N, p.M, p.P, p.Q);
+        if (st != COVEST_OK) return fail(st, "problem %lld: %s", (long long)i, g_err.c_str());
+        if (!p.A || !p.R) return fail(COVEST_ERR_INVALID_ARG, "problem %lld: null A or R", (long long)i);
+        if (p.lda < p.M || p.ldr < (int64_t)p.P * p.Q)
+            return fail(COVEST_ERR_INVALID_ARG, "problem %lld: lda %lld < M or ldr %lld < PQ", (long long)i,
+                        (long long)p.lda, (long long)p.ldr);
+        if (p.P > kMaxWindow || p.Q > kMaxWindow)
+            return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: P, Q <= %d", (long long)i, kMaxWindow);
+    }
+    covest_plan *plan = new covest_plan();
+    plan->opts = o;
+    plan->count = count;
+    st = build_batched(plan, problems, count, o, stream);
+    if (st != COVEST_OK) {
+        const std::string msg = g_err;
+        free_plan(plan);
+        return fail(st, "%s", msg.c_str());
+    }
+    *out = plan;
+    return ok();
 }
 
 }  // namespace
@@ -1089,32 +1125,60 @@ int covest_plan_batched_create(covest_plan **out, const covest_problem *problems
 {
     if (!out || !problems || count < 1) return fail(COVEST_ERR_INVALID_ARG, "need out, problems and count >= 1");
     *out = nullptr;
-    covest_opts o = resolve_opts(opts);
-    int st = check_opts(o);
-    if (st != COVEST_OK) return st;
-    if (o.form == COVEST_FORM_HANKEL_MFMA)
-        return fail(COVEST_ERR_UNSUPPORTED, "batched plans use the recurrence form");
-    if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
-        return fail(COVEST_ERR_UNSUPPORTED, "batched plans compute in FP64 (prec FP64 or FP32 output)");
+    std::vector<covest_problem_ex> ex((size_t)count);
     for (int64_t i = 0; i < count; ++i) {
         const covest_problem &p = problems[i];
-        st = check_shape(p.N, p.M, p.P, p.Q);
-        if (st != COVEST_OK) return fail(st, "problem %lld: %s", (long long)i, g_err.c_str());
-        if (!p.A || !p.R) return fail(COVEST_ERR_INVALID_ARG, "problem %lld: null A or R", (long long)i);
-        if (p.P > kMaxWindow || p.Q > kMaxWindow)
-            return fail(COVEST_ERR_UNSUPPORTED, "problem %lld: P, Q <= %d", (long long)i, kMaxWindow);
+        ex[i] = covest_problem_ex{p.A, p.R, (int64_t)p.M, (int64_t)p.P * p.Q, p.N, p.M, p.P, p.Q};
     }
-    covest_plan *plan = new covest_plan();
-    plan->opts = o;
-    plan->count = count;
-    st = build_batched(plan, problems, count, o, stream);
-    if (st != COVEST_OK) {
-        const std::string msg = g_err;
-        free_plan(plan);
-        return fail(st, "%s", msg.c_str());
-    }
-    *out = plan;
-    return ok();
+    return create_batched(out, ex.data(), count, opts, stream);
+}
+
+int covest_plan_batched_create_ex(covest_plan **out, const covest_problem_ex *problems, int64_t count,
+                                  const covest_opts *opts, hipStream_t stream)
+{
+    if (!out || !problems || count < 1) return fail(COVEST_ERR_INVALID_ARG, "need out, problems and count >= 1");
+    *out = nullptr;
+    return create_batched(out, problems, count, opts, stream);
+}
+
+int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *grid, int64_t P, int64_t Q,
+                                 void *R, const covest_opts *opts, hipStream_t stream)
+{
+    if (!out || !grid || !grid->image || !R) return fail(COVEST_ERR_INVALID_ARG, "need out, grid, image and R");
+    *out = nullptr;
+    const covest_aperture_grid &g = *grid;
+    if (g.H < 1 || g.W < 1 || g.ld < g.W)
+        return fail(COVEST_ERR_INVALID_ARG, "image %lld x %lld with ld %lld", (long long)g.H, (long long)g.W,
+                    (long long)g.ld);
+    if (g.n_rows < 1 || g.n_cols < 1 || g.row_step < 1 || g.col_step < 1)
+        return fail(COVEST_ERR_INVALID_ARG, "aperture counts and steps must be >= 1");
+    if (g.ap_rows < 1 || g.ap_cols < 1 || g.ap_rows > g.H || g.ap_cols > g.W ||
+        g.n_rows - 1 > (g.H - g.ap_rows) / g.row_step || g.n_cols - 1 > (g.W - g.ap_cols) / g.col_step)
+        return fail(COVEST_ERR_SHAPE, "%lld x %lld apertures of %lld x %lld at steps %lld, %lld leave the %lld x %lld image",
+                    (long long)g.n_rows, (long long)g.n_cols, (long long)g.ap_rows, (long long)g.ap_cols,
+                    (long long)g.row_step, (long long)g.col_step, (long long)g.H, (long long)g.W);
+    if (g.n_rows > INT32_MAX / g.n_cols) return fail(COVEST_ERR_SHAPE, "more than 2^31 - 1 apertures");
+    int st = check_shape(g.ap_rows, g.ap_cols, P, Q);
+    if (st != COVEST_OK) return st;
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
+    const covest_opts o = resolve_opts(opts);
+    const size_t esz = o.prec == COVEST_PREC_FP64 ? 16 : 8;
+    const int64_t pq = P * Q, count = g.n_rows * g.n_cols;
+    std::vector<covest_problem_ex> ex((size_t)count);
+    for (int64_t a = 0; a < g.n_rows; ++a)
+        for (int64_t b = 0; b < g.n_cols; ++b) {
+            const int64_t i = a * g.n_cols + b;
+            ex[i].A = static_cast<const char *>(g.image) + 8 * (a * g.row_step * g.ld + b * g.col_step);
+            ex[i].R = static_cast<char *>(R) + esz * (size_t)(i * pq * pq);
+            ex[i].lda = g.ld;
+            ex[i].ldr = pq;
+            ex[i].N = (int32_t)g.ap_rows;
+            ex[i].M = (int32_t)g.ap_cols;
+            ex[i].P = (int32_t)P;
+            ex[i].Q = (int32_t)Q;
+        }
+    return create_batched(out, ex.data(), count, opts, stream);
 }
 
 int covest_forward_batched(covest_plan *plan, hipStream_t stream)

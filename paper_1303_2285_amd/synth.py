@@ -21,6 +21,10 @@ P x Q sliding window):
                     from {4, 8, 12, 16}
 * ``adjoint``       512x512 Gaussian A, a random Hermitian W and the R of an
                     independent input (loss of the differentiation workload)
+* ``aperture_image`` one large image of 2-D exponentials plus noise, cut into
+                    a grid of overlapping apertures (the many-matrix imaging
+                    workload of Sec. 2.3: a 1600x1600 image, 25x25 apertures of
+                    100x100, a 10x10 window)
 
 The 2-D exponentials stand in for the spectral-estimation signals the paper
 cites (Sec. 2.3); no SAR data or benchmark suite is involved.
@@ -31,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "gaussian", "small_int", "exponentials", "wide_range", "batch_shapes",
-    "batch", "adjoint_inputs", "hermitian", "CONFIGS",
+    "batch", "adjoint_inputs", "hermitian", "aperture_image", "CONFIGS", "APERTURE_GRIDS",
 ]
 
 
@@ -137,6 +141,20 @@ def adjoint_inputs(N: int = 512, M: int = 512, P: int = 16, Q: int = 16,
     W = hermitian(P * Q, seed_w)
     At = gaussian(N, M, seed_t)
     return A, W, At
+
+
+def aperture_image(H: int, W: int, seed: int, n_exp: int = 8, noise_var: float = 0.1) -> np.ndarray:
+    """An H x W image for the aperture workload: ``n_exp`` unit-amplitude 2-D
+    exponentials (point scatterers seen in the frequency domain) plus complex
+    noise 10 dB below one of them.  A synthetic stand-in for imaging data."""
+    return exponentials(H, W, seed, n_exp, noise_var)
+
+
+# name -> (H, W, ap_rows, ap_cols, row_step, col_step, n_rows, n_cols, P, Q, seed):
+# aperture (a, b) is image[a*row_step : a*row_step + ap_rows, b*col_step : ...]
+APERTURE_GRIDS = {
+    "sar_1600": (1600, 1600, 100, 100, 62, 62, 25, 25, 10, 10, 6),
+}
 
 
 # name -> (N, M, P, Q, generator, seed)

@@ -108,3 +108,56 @@ def test_timing_calls_without_device():
     cv.timing_reset()
     assert cv.timing_read() == {}
     cv.timing_enable(False)
+
+
+def test_batched_and_aperture_argument_errors_before_device_use():
+    L = cv.lib()
+    o = _opts()
+    plan = ctypes.c_void_p(0)
+    p = cv.covest_problem_ex(16, 16, 64, 64, 64, 64, 8, 8)
+    arr = (cv.covest_problem_ex * 1)(p)
+    assert L.covest_plan_batched_create_ex(None, arr, 1, o, None) == cv.ERR_INVALID_ARG
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 0, o, None) == cv.ERR_INVALID_ARG
+    arr[0].lda = 63
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 1, o, None) == cv.ERR_INVALID_ARG
+    assert "lda" in L.covest_last_error().decode()
+    arr[0].lda, arr[0].ldr = 64, 63
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 1, o, None) == cv.ERR_INVALID_ARG
+    arr[0].ldr, arr[0].P = 64, 65
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 1, o, None) == cv.ERR_SHAPE
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 1, _opts(form="hankel", precision="fp32"),
+                                           None) == cv.ERR_UNSUPPORTED
+    assert plan.value is None
+
+    def grid(**kw):
+        g = dict(ld=1600, H=1600, W=1600, ap_rows=100, ap_cols=100, row_step=62, col_step=62, n_rows=25,
+                 n_cols=25)
+        g.update(kw)
+        return cv.covest_aperture_grid(16, *[g[k] for k in ("ld", "H", "W", "ap_rows", "ap_cols", "row_step",
+                                                            "col_step", "n_rows", "n_cols")])
+
+    def create(g, P=10, Q=10, R=16, opts=o):
+        return L.covest_plan_apertures_create(ctypes.byref(plan), ctypes.byref(g), P, Q, ctypes.c_void_p(R),
+                                              opts, None)
+
+    assert L.covest_plan_apertures_create(ctypes.byref(plan), None, 10, 10, ctypes.c_void_p(16), o, None) \
+        == cv.ERR_INVALID_ARG
+    assert create(grid(), R=0) == cv.ERR_INVALID_ARG
+    assert create(grid(ld=1599)) == cv.ERR_INVALID_ARG
+    assert create(grid(row_step=0)) == cv.ERR_INVALID_ARG
+    assert create(grid(n_cols=0)) == cv.ERR_INVALID_ARG
+    # the last aperture row starts at 24 * 63 = 1512 and ends at 1612 > 1600
+    assert create(grid(row_step=63)) == cv.ERR_SHAPE
+    assert "leave" in L.covest_last_error().decode()
+    assert create(grid(col_step=63)) == cv.ERR_SHAPE
+    assert create(grid(ap_rows=1601)) == cv.ERR_SHAPE
+    assert create(grid(), P=101) == cv.ERR_SHAPE
+    assert create(grid(ld=1 << 20, H=1 << 20, W=1 << 20, ap_rows=1, ap_cols=1, row_step=1, col_step=1,
+                       n_rows=1 << 16, n_cols=1 << 16), P=1, Q=1) == cv.ERR_SHAPE
+    assert "2^31" in L.covest_last_error().decode()
+    assert create(grid(), P=80, Q=80) == cv.ERR_UNSUPPORTED
+    assert create(grid(), opts=_opts(form="hankel", precision="fp32")) == cv.ERR_UNSUPPORTED
+    # the largest grid that fits: the last aperture ends exactly at the image edge
+    assert create(grid(row_step=62, n_rows=25, H=24 * 62 + 100), opts=_opts(precision="fp16")) \
+        == cv.ERR_UNSUPPORTED
+    assert plan.value is None

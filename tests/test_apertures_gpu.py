@@ -1,0 +1,202 @@
+"""GPU parity of the many-matrix workloads over strided views: R for every
+aperture of one image (covest_plan_apertures_create) and batches of windows
+into larger arrays (covest_plan_batched_create_ex), against the CPU oracle run
+on each aperture as a contiguous copy.
+
+Bar: bit-exact on small-integer images (every FP64 sum is an integer below
+2^53, one IEEE division per part); relative Frobenius error below 1e-12 on
+float images (same exact products, another summation order); every R exactly
+Hermitian with a real diagonal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1303_2285_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+
+def _note(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cv():
+    from paper_1303_2285_amd import covest
+    covest.lib()
+    return covest
+
+
+def relF(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def aperture(img, a, b, ap, step):
+    r0, c0 = a * step[0], b * step[1]
+    return np.ascontiguousarray(img[r0:r0 + ap[0], c0:c0 + ap[1]])
+
+
+def run_grid(cv, torch_dev, img, ap, step, n, P, Q, **kw):
+    torch, dev = torch_dev
+    plan = cv.AperturePlan(torch.from_numpy(img).to(dev), ap[0], ap[1], step[0], step[1], n[0], n[1], P, Q, **kw)
+    R = plan.run()
+    torch.cuda.synchronize()
+    out = R.cpu().numpy()
+    plan.close()
+    return out
+
+
+def trace_identity(A, P, Q):
+    """tr R from the weights of each element (independent of the oracle)."""
+    N, M = A.shape
+    Kr, Kc = N - P + 1, M - Q + 1
+    wr = np.minimum(Kr - 1, np.arange(N)) - np.maximum(0, np.arange(N) - P + 1) + 1
+    wc = np.minimum(Kc - 1, np.arange(M)) - np.maximum(0, np.arange(M) - Q + 1) + 1
+    return (np.abs(A.astype(np.complex128)) ** 2 * wr[:, None] * wc[None, :]).sum() / (Kr * Kc)
+
+
+@pytest.mark.parametrize("engine", ["auto", "vector"])
+def test_small_grid_integer_bit_exact(cv, torch_dev, oracle_mod, engine):
+    """6 x 6 overlapping 30 x 25 apertures of a 90 x 80 image, 5 x 4 window."""
+    img = synth.small_int(90, 80, seed=71)
+    ap, step, n, P, Q = (30, 25), (12, 11), (6, 6), 5, 4
+    _note("aperture grid 90x80 ap 30x25 step 12x11", engine)
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q, engine=engine)
+    assert R.shape == (6, 6, P * Q, P * Q)
+    for a in range(n[0]):
+        for b in range(n[1]):
+            ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q)
+            assert np.array_equal(R[a, b], ref), (a, b)
+
+
+@pytest.mark.parametrize("engine", ["auto", "matrix"])
+def test_matrix_engine_grid_integer_bit_exact(cv, torch_dev, oracle_mod, engine):
+    """4 x 4 apertures of 64 x 60 with a 16 x 16 window: the matrix-core
+    engine reads every aperture through the image's row stride."""
+    img = synth.small_int(160, 150, seed=72)
+    ap, step, n, P, Q = (64, 60), (32, 30), (4, 4), 16, 16
+    _note("aperture grid 160x150 ap 64x60 step 32x30 P=Q=16", engine)
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q, engine=engine)
+    for a in range(n[0]):
+        for b in range(n[1]):
+            ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q, threads=oracle_mod.max_threads())
+            assert np.array_equal(R[a, b], ref), (a, b)
+
+
+def test_single_aperture_and_edges(cv, torch_dev, oracle_mod):
+    """One aperture equal to the whole image; apertures of one row; a window
+    as large as the aperture (K = 1); 1 x 1 windows."""
+    img = synth.small_int(40, 36, seed=73)
+    _note("aperture edge grids")
+    R = run_grid(cv, torch_dev, img, (40, 36), (1, 1), (1, 1), 6, 5)
+    assert np.array_equal(R[0, 0], oracle_mod.forward(img, 6, 5))
+    R = run_grid(cv, torch_dev, img, (40, 9), (1, 3), (1, 10), 4, 3)
+    for b in range(10):
+        assert np.array_equal(R[0, b], oracle_mod.forward(aperture(img, 0, b, (40, 9), (1, 3)), 4, 3))
+    R = run_grid(cv, torch_dev, img, (7, 6), (5, 5), (7, 7), 7, 6)
+    for a in range(7):
+        for b in range(7):
+            assert np.array_equal(R[a, b], oracle_mod.forward(aperture(img, a, b, (7, 6), (5, 5)), 7, 6))
+    R = run_grid(cv, torch_dev, img, (10, 10), (3, 2), (11, 14), 1, 1)
+    for a in range(11):
+        for b in range(14):
+            assert np.array_equal(R[a, b], oracle_mod.forward(aperture(img, a, b, (10, 10), (3, 2)), 1, 1))
+
+
+def test_float_grid_fp32_output_and_upper_fill(cv, torch_dev, oracle_mod):
+    img = synth.aperture_image(120, 110, seed=74)
+    ap, step, n, P, Q = (48, 40), (18, 14), (5, 6), 8, 6
+    _note("aperture grid float fp32 output / upper fill")
+    R32 = run_grid(cv, torch_dev, img, ap, step, n, P, Q, precision="fp32")
+    Ru = run_grid(cv, torch_dev, img, ap, step, n, P, Q, fill="upper")
+    assert R32.dtype == np.complex64
+    iu, il = np.triu_indices(P * Q), np.tril_indices(P * Q, -1)
+    for a in range(n[0]):
+        for b in range(n[1]):
+            ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q)
+            # FP64 sums rounded once to float
+            assert np.abs(R32[a, b] - ref).max() <= 2 ** -23 * np.abs(ref).max()
+            assert np.array_equal(R32[a, b], R32[a, b].conj().T)
+            assert relF(Ru[a, b][iu], ref[iu]) <= TOL_FP64
+            assert np.all(Ru[a, b][il] == 0)
+
+
+def test_strided_batch_mixed_shapes(cv, torch_dev, oracle_mod):
+    """A batch of views into one array (row stride 300) plus a contiguous
+    input, uneven shapes and windows, both engines in one plan."""
+    torch, dev = torch_dev
+    big = synth.small_int(260, 300, seed=75)
+    Bt = torch.from_numpy(big).to(dev)
+    views = [((0, 0, 100, 120), 8, 8), ((37, 51, 90, 77), 12, 5), ((120, 10, 140, 290), 16, 16),
+             ((5, 200, 64, 64), 4, 4), ((250, 0, 10, 300), 3, 7), ((100, 100, 33, 33), 16, 16)]
+    problems, refs = [], []
+    for (r0, c0, N, M), P, Q in views:
+        problems.append((Bt[r0:r0 + N, c0:c0 + M], P, Q))
+        refs.append(oracle_mod.forward(np.ascontiguousarray(big[r0:r0 + N, c0:c0 + M]), P, Q,
+                                       threads=oracle_mod.max_threads()))
+    A7 = synth.small_int(70, 50, seed=76)
+    problems.append((torch.from_numpy(A7).to(dev), 6, 9))
+    refs.append(oracle_mod.forward(A7, 6, 9))
+    assert problems[2][0].stride(0) == 300
+    _note("strided batch, 7 problems")
+    plan = cv.BatchedPlan(problems)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for i, (R, ref) in enumerate(zip(outs, refs)):
+        assert np.array_equal(R.cpu().numpy(), ref), i
+    plan.close()
+
+
+def test_sar_grid_full_size(cv, torch_dev, oracle_mod):
+    """The imaging workload as timed: a 1600 x 1600 image, 25 x 25 apertures
+    of 100 x 100 (step 62), 10 x 10 window, 625 R matrices.  Sampled
+    apertures against the oracle; every aperture Hermitian, real diagonal and
+    its trace against the trace identity; a repeat replay bit-identical."""
+    torch, dev = torch_dev
+    H, W, ar, ac, sr, sc, nr, nc, P, Q, seed = synth.APERTURE_GRIDS["sar_1600"]
+    img = synth.aperture_image(H, W, seed)
+    _note("sar_1600 aperture grid, 625 apertures")
+    plan = cv.AperturePlan(torch.from_numpy(img).to(dev), ar, ac, sr, sc, nr, nc, P, Q)
+    R1 = plan.run().cpu().numpy()
+    R2 = plan.run().cpu().numpy()
+    plan.close()
+    assert np.array_equal(R1, R2)
+    rng = np.random.default_rng(6)
+    picks = [(0, 0), (nr - 1, nc - 1), (0, nc - 1), (nr - 1, 0)] + \
+        [tuple(x) for x in rng.integers(0, [nr, nc], size=(6, 2))]
+    for a, b in picks:
+        ref = oracle_mod.forward(aperture(img, a, b, (ar, ac), (sr, sc)), P, Q, threads=oracle_mod.max_threads())
+        assert relF(R1[a, b], ref) <= TOL_FP64, (a, b)
+    assert np.array_equal(R1, np.conj(np.swapaxes(R1, 2, 3)))
+    d = np.diagonal(R1, axis1=2, axis2=3)
+    assert np.all(d.imag == 0)
+    for a in range(nr):
+        for b in range(nc):
+            tr = trace_identity(aperture(img, a, b, (ar, ac), (sr, sc)), P, Q)
+            assert abs(d[a, b].real.sum() - tr) <= 1e-12 * tr, (a, b)
+
+
+def test_sar_grid_full_size_integer_bit_exact(cv, torch_dev, oracle_mod):
+    """The same geometry on a small-integer image: sampled apertures bit-exact."""
+    torch, dev = torch_dev
+    H, W, ar, ac, sr, sc, nr, nc, P, Q, _ = synth.APERTURE_GRIDS["sar_1600"]
+    img = synth.small_int(H, W, seed=77)
+    _note("sar_1600 geometry, integer image")
+    R = run_grid(cv, torch_dev, img, (ar, ac), (sr, sc), (nr, nc), P, Q)
+    rng = np.random.default_rng(77)
+    picks = [(0, 0), (nr - 1, nc - 1)] + [tuple(x) for x in rng.integers(0, [nr, nc], size=(6, 2))]
+    for a, b in picks:
+        ref = oracle_mod.forward(aperture(img, a, b, (ar, ac), (sr, sc)), P, Q, threads=oracle_mod.max_threads())
+        assert np.array_equal(R[a, b], ref), (a, b)
