@@ -29,8 +29,9 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kFinMaxRows = 160;   // individual rows the table finalize handles (n_ir)
 // finalize variants: LDS table (16 corner loads per thread in flight), one
 // wave per combination, LDS table for at most kFinSmallCorners corner
-// products, wave prefix sums (at most 63 individual columns and 63 rows)
-enum { kFinTable = 0, kFinLean = 1, kFinTableSmall = 2, kFinScan = 3, kFinVariants = 4 };
+// products, wave prefix sums (at most 63 individual columns and 63 rows),
+// wave prefix sums for at most 31 individual rows (fewer registers)
+enum { kFinTable = 0, kFinLean = 1, kFinTableSmall = 2, kFinScan = 3, kFinScanSmall = 4, kFinVariants = 5 };
 constexpr int kFinSmallCorners = 4 * 256;
 
 // A set of lanes of one wave slot: lane li has

@@ -108,6 +108,10 @@ static void finish_plan(ShapePlan &sp, BulkRange bulk_range)
         sp.fin_variant = kFinScan;
         sp.lds_fin = (size_t)Q * ((1 + sp.n_ir) | 1) * 16;
     }
+    if (sp.n_ic <= 63 && sp.n_ir <= 31) {
+        sp.fin_variant = kFinScanSmall;
+        sp.lds_fin = (size_t)Q * ((1 + sp.n_ir) | 1) * 16;
+    }
 
     sp.ws_bytes = (size_t)16 * sp.lag_stride *
                   ((size_t)sp.n_bulk + (size_t)sp.zpieces * ((size_t)sp.n_ir + (size_t)sp.n_ic));

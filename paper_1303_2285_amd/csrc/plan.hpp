@@ -35,7 +35,7 @@ struct ShapePlan {
     std::vector<FinItem> items;
     std::vector<double> job_cost;        // estimated wave-steps per job
     size_t lds_main = 0, lds_fin = 0;
-    int fin_variant = 1;                 // kFinTable, kFinLean or kFinTableSmall
+    int fin_variant = 1;                 // kFinTable, kFinLean, kFinTableSmall, kFinScan or kFinScanSmall
     size_t ws_bytes = 0;                 // partial + zr + zc, FP64 complex
     int64_t main_products = 0;           // distinct products the main kernel keeps
     int64_t fin_products = 0;            // corner products the finalize computes

@@ -673,10 +673,12 @@ __device__ __forceinline__ double2 range_sum(double2 *row, double2 e, int lo, in
 // Only the classes' sums per offset live in LDS (nc x (1 + n_ir)); the corner
 // products never do.  Rows and columns a lag cannot use are zeroed before
 // the sums, so the differences of prefix sums cancel exactly what they should.
-template <bool INLINE>
+template <bool INLINE, int KCLS>
 __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
 {
-    constexpr int kCls = 16;   // classes per wave at most (64 / 4 waves)
+    // classes per wave at most: 16 (1 + n_ir <= 64) or 8 (1 + n_ir <= 32, fewer
+    // registers, so more workgroups per CU hide the loads of small tables)
+    constexpr int kCls = KCLS;
     extern __shared__ double2 St[];
     __shared__ double2 red[4];
     __shared__ double2 xch[4][64];   // per wave: the prefix sums, read back at two lanes
@@ -793,8 +795,10 @@ hipError_t prepare_rec_kernels()
                              reinterpret_cast<const void *>(&rec_finalize),
                              reinterpret_cast<const void *>(&rec_finalize_tab<16, 8>),
                              reinterpret_cast<const void *>(&rec_finalize_tab<4, 4>),
-                             reinterpret_cast<const void *>(&rec_finalize_scan<true>),
-                             reinterpret_cast<const void *>(&rec_finalize_scan<false>)};
+                             reinterpret_cast<const void *>(&rec_finalize_scan<true, 16>),
+                             reinterpret_cast<const void *>(&rec_finalize_scan<false, 16>),
+                             reinterpret_cast<const void *>(&rec_finalize_scan<true, 8>),
+                             reinterpret_cast<const void *>(&rec_finalize_scan<false, 8>)};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
             if (e != hipSuccess) return e;
@@ -834,9 +838,13 @@ hipError_t launch_rec_finalize(const FinArgs &fa, int n_blocks, size_t lds_bytes
     else if (variant == kFinTableSmall)
         hipLaunchKernelGGL((rec_finalize_tab<4, 4>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else if (variant == kFinScan && fa.use_inline)
-        hipLaunchKernelGGL(rec_finalize_scan<true>, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+        hipLaunchKernelGGL((rec_finalize_scan<true, 16>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else if (variant == kFinScan)
-        hipLaunchKernelGGL(rec_finalize_scan<false>, dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+        hipLaunchKernelGGL((rec_finalize_scan<false, 16>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else if (variant == kFinScanSmall && fa.use_inline)
+        hipLaunchKernelGGL((rec_finalize_scan<true, 8>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
+    else if (variant == kFinScanSmall)
+        hipLaunchKernelGGL((rec_finalize_scan<false, 8>), dim3(n_blocks), dim3(256), lds_bytes, stream, fa);
     else
         hipLaunchKernelGGL(rec_finalize, dim3(n_blocks), dim3(64), lds_bytes, stream, fa);
     return hipGetLastError();
