@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=8, help="timed calls per plain-form precision")
     ap.add_argument("--no-plain", action="store_true", help="skip the matrix-core plain forms")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, aperture and adjoint workloads")
+    ap.add_argument("--extras", default="batched,apertures,adjoint",
+                    help="comma-separated subset of the secondary workloads to run")
     ap.add_argument("--no-vector", action="store_true",
                     help="skip the comparison run of the recurrence on the vector engine")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -165,12 +167,23 @@ def cpu_leg(A, eta, seconds, k1s, k2s, gpu_values, noise_power):
 import numpy as np  # noqa: E402
 
 
-def extra_workloads(covest, synth, torch, dev):
+def extra_workloads(covest, synth, torch, dev, which):
     """The batch workload (512 uneven problems in one graph replay), the
     imaging workload (R of every aperture of one image, one graph replay) and
     the differentiation workload (512 x 512, 16 x 16: forward + adjoint)."""
     out = {}
-    batch = synth.batch(512, seed=4)
+    reps = 10
+    if "batched" in which:
+        out.update(_batched(covest, torch, dev, synth.batch(512, seed=4), reps))
+    if "apertures" in which:
+        out.update(_apertures(covest, synth, torch, dev, reps))
+    if "adjoint" in which:
+        out.update(_adjoint(covest, synth, torch, dev))
+    return out
+
+
+def _batched(covest, torch, dev, batch, reps):
+    out = {}
     As = [torch.from_numpy(A).to(dev) for (A, P, Q) in batch]
     t0 = time.perf_counter()
     plan = covest.BatchedPlan([(At, P, Q) for At, (A, P, Q) in zip(As, batch)])
@@ -178,7 +191,6 @@ def extra_workloads(covest, synth, torch, dev):
     for _ in range(2):
         plan.run()
     torch.cuda.synchronize()
-    reps = 10
     t0 = time.perf_counter()
     for _ in range(reps):
         plan.run()
@@ -191,7 +203,11 @@ def extra_workloads(covest, synth, torch, dev):
                       "gflops_algorithmic": 8.0 * um / dt / 1e9, "plan_s": t_plan}
     print(f"[bench] batched: {dt * 1e3:.3f} ms per 512 matrices", file=sys.stderr, flush=True)
     plan.close()
-    del As
+    return out
+
+
+def _apertures(covest, synth, torch, dev, reps):
+    out = {}
     H, W_img, ar, ac, sr, sc, nr, nc, Pa, Qa, seed = synth.APERTURE_GRIDS["sar_1600"]
     img = torch.from_numpy(synth.aperture_image(H, W_img, seed)).to(dev)
     t0 = time.perf_counter()
@@ -216,7 +232,11 @@ def extra_workloads(covest, synth, torch, dev):
                         "r_write_gb_s": n_ap * (Pa * Qa) ** 2 * 16 / dt / 1e9, "plan_s": t_plan}
     print(f"[bench] apertures: {dt * 1e3:.3f} ms per image ({n_ap} matrices)", file=sys.stderr, flush=True)
     plan.close()
-    del img
+    return out
+
+
+def _adjoint(covest, synth, torch, dev):
+    out = {}
     A, W, At = synth.adjoint_inputs()
     Ad = torch.from_numpy(A).to(dev)
     G = torch.from_numpy(W.astype(np.complex64)).to(dev)
@@ -242,8 +262,8 @@ def extra_workloads(covest, synth, torch, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the path is single-GPU; see the design notes for how it would shard)",
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the library runs the path on one GPU; the design notes describe how it would shard)",
               file=sys.stderr, flush=True)
         sys.exit(2)
     if args.copy_calibration:
@@ -365,7 +385,7 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        extra = extra_workloads(covest, synth, torch, dev)
+        extra = extra_workloads(covest, synth, torch, dev, set(args.extras.split(",")))
 
     f_nom = 8.0 * cnt["K"] * cnt["eta"]         # plain-form flops: every product recomputed
     f_alg = 8.0 * cnt["um"]                     # each distinct product once
