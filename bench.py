@@ -62,6 +62,8 @@ def parse():
                     help="comma-separated subset of the secondary workloads to run")
     ap.add_argument("--no-vector", action="store_true",
                     help="skip the comparison run of the recurrence on the vector engine")
+    ap.add_argument("--worker-scaling", action="store_true",
+                    help="only run the worker-count study (Sec. 5.1, Fig. 4 sizes) and print its table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 256 MiB (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
@@ -259,6 +261,49 @@ def _adjoint(covest, synth, torch, dev):
     return out
 
 
+def worker_scaling():
+    """Speedup against the number of workers (Sec. 5.1, Fig. 4): the paper's two
+    windows (8 x 8 and 13 x 13) on 64 x 64 and 128 x 128 inputs, as one matrix
+    and as 8 and 64 independent matrices, each run as a batched plan on the
+    vector engine whose persistent kernel is capped at w workgroups
+    (COVEST_WORKERS); the finalize is not capped.  (At the paper's own sizes,
+    20 x 20 and 32 x 32, no product falls in a middle block: the finalize
+    computes all of them, one workgroup per combination.)  Replay times come
+    from HIP events around each graph launch; the persistent kernel's own
+    times come from a rocprofv3 kernel trace of this run."""
+    os.environ["COVEST_TUNE"] = "0"
+    import torch
+    from paper_1303_2285_amd import covest, synth
+    dev = torch.device("cuda:0")
+    rows = []
+    for (n, m, p, q) in [(64, 64, 8, 8), (128, 128, 13, 13)]:
+        for copies in (1, 8, 64):
+            As = [torch.from_numpy(synth.gaussian(n, m, seed=1000 + i)).to(dev) for i in range(copies)]
+            for w in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+                os.environ["COVEST_WORKERS"] = str(w)
+                plan = covest.BatchedPlan([(A, p, q) for A in As], engine="vector")
+                for _ in range(2):
+                    plan.run()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(10):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    plan.run()
+                    b.record()
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                plan.close()
+                ts.sort()
+                rows.append({"N": n, "M": m, "P": p, "Q": q, "copies": copies, "workers": w,
+                             "replay_ms_median": ts[len(ts) // 2]})
+                print(f"[scaling] {n}x{m}/{p}x{q} x{copies} workers {w}: {ts[len(ts) // 2]:.4f} ms",
+                      file=sys.stderr, flush=True)
+    os.environ.pop("COVEST_WORKERS", None)
+    print(json.dumps({"study": "worker scaling", "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -266,6 +311,9 @@ def main():
               "(the library runs the path on one GPU; the design notes describe how it would shard)",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.worker_scaling:
+        worker_scaling()
+        return
     if args.copy_calibration:
         copy_calibration()
         return

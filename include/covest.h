@@ -162,7 +162,10 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
  * instance.  The A and R buffers named at creation must stay valid.
  * opts->engine applies per problem as for a single call (AUTO: the matrix
  * cores wherever they fit; MATRIX: an error if some problem does not fit).
- * Matrix-core problems run in one extra launch per lag-block shape. */
+ * Matrix-core problems run in one extra launch per lag-block shape.
+ * Measurement knob: COVEST_WORKERS=n in the environment when a plan is
+ * created caps the persistent vector kernel at n workgroups (n >= 1); the
+ * results do not change, only how many workers claim the jobs. */
 int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,
                                const covest_opts *opts, hipStream_t stream);
 int covest_forward_batched(covest_plan *plan, hipStream_t stream);

@@ -540,6 +540,17 @@ bool g_tune_loaded = false;
 
 const char *tune_path() { return std::getenv("COVEST_TUNE_CACHE"); }
 
+// COVEST_WORKERS=n (n >= 1), read when a batched plan is built, caps the
+// persistent kernel at n workgroups: every job still runs, claimed by n
+// workers (speedup against the number of workers, as in Sec. 5.1, Fig. 4).
+int worker_cap()
+{
+    const char *s = std::getenv("COVEST_WORKERS");
+    if (!s || !*s) return 0;
+    const long n = std::strtol(s, nullptr, 10);
+    return n > 0 && n <= (1 << 20) ? (int)n : 0;
+}
+
 void tune_load_locked()
 {
     if (g_tune_loaded) return;
@@ -879,6 +890,7 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
     plan->n_jobs = (int)sorted.size();
     for (int v = 0; v < kFinVariants; ++v) plan->n_items[v] = (int)items[v].size();
     plan->grid = std::max(1, std::min(resident, plan->n_jobs));
+    if (const int cap = worker_cap()) plan->grid = std::min(plan->grid, cap);
     HIP_TRY(upload(&plan->d_jobs, sorted));
     HIP_TRY(upload(&plan->d_groups, groups));
     HIP_TRY(upload(&plan->d_insts, insts));

@@ -63,6 +63,25 @@ def test_integer_batch_bit_exact(cv, tdev, oracle_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("workers", [1, 3])
+def test_worker_cap_bit_exact(cv, tdev, oracle_mod, monkeypatch, workers):
+    """COVEST_WORKERS caps the persistent kernel's workgroups (the worker
+    study); every job still runs, so every result is still the oracle's."""
+    torch, dev = tdev
+    batch = int_batch(12, 11) + [(synth.small_int(32, 32, seed=1300), 13, 13),
+                                 (synth.small_int(20, 20, seed=1301), 8, 8)]
+    monkeypatch.setenv("COVEST_WORKERS", str(workers))
+    _note("batched integer x14, workers", workers)
+    plan = cv.BatchedPlan([(torch.from_numpy(A).to(dev), P, Q) for (A, P, Q) in batch], engine="vector")
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for (A, P, Q), R in zip(batch, outs):
+        ref = oracle_mod.forward(A, P, Q)
+        got = R.cpu().numpy()
+        assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag), (A.shape, P, Q)
+    plan.close()
+
+
 def test_workload_batch(cv, tdev, oracle_mod):
     torch, dev = tdev
     batch = synth.batch(512, seed=4)
