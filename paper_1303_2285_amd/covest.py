@@ -394,12 +394,27 @@ def _make_autograd():
 _covest_fn = None
 
 
-def covest_apply(A, P, Q, precision="fp64", normalize=True):
-    """Differentiable forward: CovEst.apply(A, P, Q, precision, normalize)."""
+def _autograd_fn():
     global _covest_fn
     if _covest_fn is None:
         _covest_fn = _make_autograd()
-    return _covest_fn.apply(A, P, Q, precision, normalize)
+    return _covest_fn
+
+
+def covest_apply(A, P, Q, precision="fp64", normalize=True):
+    """Differentiable forward: CovEst.apply(A, P, Q, precision, normalize)."""
+    return _autograd_fn().apply(A, P, Q, precision, normalize)
+
+
+# short names: covest.forward(A, P, Q), covest.backward(A, dR, P, Q), covest.CovEst.apply(A, P, Q)
+forward = covest_forward
+backward = covest_backward
+
+
+def __getattr__(name):
+    if name == "CovEst":
+        return _autograd_fn()
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
 
 
 # ---------------------------------------------------------------- timing ----

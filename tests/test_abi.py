@@ -161,3 +161,12 @@ def test_batched_and_aperture_argument_errors_before_device_use():
     assert create(grid(row_step=62, n_rows=25, H=24 * 62 + 100), opts=_opts(precision="fp16")) \
         == cv.ERR_UNSUPPORTED
     assert plan.value is None
+
+
+def test_binding_short_names():
+    import torch
+    assert cv.forward is cv.covest_forward and cv.backward is cv.covest_backward
+    assert issubclass(cv.CovEst, torch.autograd.Function)
+    assert cv.CovEst is cv.CovEst
+    with pytest.raises(AttributeError):
+        cv.no_such_name

@@ -168,7 +168,7 @@ def _fd_block(cv, tdev, oracle_mod, r0, c0, size=32):
                 fd[i, j] += g if part == 0 else 1j * g
     # analytic gradient through the adjoint
     Ag = torch.from_numpy(A).to(dev).requires_grad_(True)
-    Rg = cv.covest_apply(Ag, P, Q)
+    Rg = cv.CovEst.apply(Ag, P, Q, "fp64", True)
     L = (Wt * Rg.transpose(0, 1)).sum().real + ((Rg - Rtt).abs() ** 2).sum()
     L.backward()
     got = Ag.grad.cpu().numpy()[r0:r0 + size, c0:c0 + size].astype(np.complex128)
