@@ -192,3 +192,24 @@ def adjoint_blas(A, G, P: int, Q: int, normalize: bool = True) -> np.ndarray:
     if normalize:
         dA /= float(Kr * Kc)
     return dA
+
+
+def capon(R, P: int, Q: int, F1: int, F2: int) -> np.ndarray:
+    """Minimum-variance (Capon) spectrum of one R (Sec. 2.3 names the MVM /
+    Capon estimator as the consumer of R): S[f1][f2] = 1 / Re(a^H R^{-1} a)
+    with a[i + P*j] = exp(1j (w1 i + w2 j)) (the window index map of eq. 2.1)
+    on the grid w = -pi + 2 pi f / F.  Written from the definition: every grid
+    vector a is formed, R^{-1} a comes from LAPACK's linear solve, then the
+    quadratic form."""
+    R = np.asarray(R, dtype=np.complex128)
+    PQ = P * Q
+    w1 = -np.pi + 2 * np.pi * np.arange(F1) / F1
+    w2 = -np.pi + 2 * np.pi * np.arange(F2) / F2
+    k = np.arange(PQ)
+    i, j = k % P, k // P
+    phase = i[:, None, None] * w1[None, :, None] + j[:, None, None] * w2[None, None, :]
+    a = np.exp(1j * phase).reshape(PQ, F1 * F2)
+    x = np.linalg.solve(R, a)
+    q = np.sum(a.conj() * x, axis=0).real
+    return (1.0 / q).reshape(F1, F2)
+
