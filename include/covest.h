@@ -210,6 +210,23 @@ typedef struct {
 int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *grid, int64_t P, int64_t Q,
                                  void *R, const covest_opts *opts, hipStream_t stream);
 
+/* Minimum-variance (Capon) spectrum of a batch of estimated covariance
+ * matrices (Sec. 2.3: R feeds the MVM / Capon estimator).  Each R is PQ x PQ
+ * complex128, row-major, Hermitian positive definite (the FP64 output of
+ * covest_forward or of a batched plan); matrix c starts at R + c*PQ*PQ.  On
+ * the grid w1 = -pi + 2 pi f1 / F1, w2 = -pi + 2 pi f2 / F2:
+ *     S[c][f1][f2] = 1 / Re(a^H R^{-1} a),   a[i + P*j] = exp(i (w1 i + w2 j)),
+ * S being count x F1 x F2 doubles (device).  Cholesky factor in FP64, R^{-1}
+ * from two triangular solves, its sums along the lags (i1 - i2, j1 - j2) and a
+ * separable 2-D DFT of those sums (the quadratic form depends on R^{-1} only
+ * through them).  Limits: PQ <= 128 (COVEST_ERR_UNSUPPORTED), 1 <= F1, F2 <=
+ * 4096 (COVEST_ERR_SHAPE).  ws holds covest_capon_workspace_size() bytes
+ * (COVEST_ERR_WORKSPACE if smaller).  A matrix that is not numerically positive
+ * definite (a Cholesky pivot <= 0 or NaN) gets an all-NaN spectrum. */
+int covest_capon_workspace_size(int64_t count, int64_t P, int64_t Q, int64_t F1, size_t *bytes);
+int covest_capon_spectrum(const void *R, int64_t count, int64_t P, int64_t Q, int64_t F1, int64_t F2, double *S,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Kernel timing for benchmarks: while enabled, every kernel the library
  * launches is bracketed by HIP events on its stream and its duration is added
  * to a per-kernel total.  covest_timing_read copies up to `cap` records (name,

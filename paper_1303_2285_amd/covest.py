@@ -110,6 +110,8 @@ SIGNATURES = {
     "covest_plan_apertures_create": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_aperture_grid), _i64,
                                             _i64, _vp, ctypes.POINTER(covest_opts), _vp]),
     "covest_forward_batched": (_int, [_vp, _vp]),
+    "covest_capon_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "covest_capon_spectrum": (_int, [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, ctypes.c_size_t, _vp]),
     "covest_plan_destroy": (_int, [_vp]),
     "covest_timing_enable": (_int, [_int]),
     "covest_timing_reset": (_int, []),
@@ -357,6 +359,31 @@ class AperturePlan(_PlanHandle):
         _check(lib().covest_plan_apertures_create(ctypes.byref(self._handle), ctypes.byref(g), int(P), int(Q),
                                                   ctypes.c_void_p(self.outputs.data_ptr()), ctypes.byref(o),
                                                   _stream_handle(image.device)))
+
+
+def covest_capon_spectrum(R, P: int, Q: int, F1: int, F2: int, *, workspace=None):
+    """Minimum-variance (Capon) spectrum 1 / Re(a^H R^{-1} a) of each R on the
+    grid w = -pi + 2 pi f / F (covest_capon_spectrum).  R: complex128 tensor of
+    shape (PQ, PQ) or (count, PQ, PQ), or a (n_rows, n_cols, PQ, PQ) aperture
+    output; returns float64 of shape R.shape[:-2] + (F1, F2)."""
+    torch = _torch()
+    if not isinstance(R, torch.Tensor) or not R.is_cuda or R.dtype != torch.complex128:
+        raise TypeError("R must be a complex128 CUDA (HIP) tensor")
+    PQ = int(P) * int(Q)
+    if R.dim() < 2 or R.shape[-2:] != (PQ, PQ):
+        raise ValueError("R must end in PQ x PQ")
+    lead = tuple(R.shape[:-2])
+    Rc = R.reshape(-1, PQ, PQ).contiguous()
+    count = Rc.shape[0]
+    S = torch.empty((count, int(F1), int(F2)), dtype=torch.float64, device=R.device)
+    n = ctypes.c_size_t(0)
+    _check(lib().covest_capon_workspace_size(count, P, Q, F1, ctypes.byref(n)))
+    ws, nbytes = _workspace(int(n.value), R.device) if workspace is None else (workspace, workspace.numel())
+    _check(lib().covest_capon_spectrum(ctypes.c_void_p(Rc.data_ptr()), count, P, Q, F1, F2,
+                                       ctypes.c_void_p(S.data_ptr()),
+                                       ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), nbytes,
+                                       _stream_handle(R.device)))
+    return S.reshape(lead + (int(F1), int(F2)))
 
 
 def covest_forward_batched(plan: BatchedPlan):

@@ -22,6 +22,7 @@
 #include "covest.h"
 #include "covest_plan.h"
 #include "adj_internal.hpp"
+#include "capon_internal.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -1191,6 +1192,43 @@ int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *
             ex[i].Q = (int32_t)Q;
         }
     return create_batched(out, ex.data(), count, opts, stream);
+}
+
+int covest_capon_workspace_size(int64_t count, int64_t P, int64_t Q, int64_t F1, size_t *bytes)
+{
+    if (!bytes) return fail(COVEST_ERR_INVALID_ARG, "bytes is null");
+    if (count < 0 || P < 1 || Q < 1 || F1 < 1 || F1 > kCaponMaxGrid)
+        return fail(COVEST_ERR_SHAPE, "need count >= 0, P, Q >= 1 and 1 <= F1 <= %d", kCaponMaxGrid);
+    if (P * Q > kCaponMaxPQ) return fail(COVEST_ERR_UNSUPPORTED, "the spectrum supports PQ <= %d", kCaponMaxPQ);
+    *bytes = (size_t)count * capon_ws_per_matrix((int)(P * Q), (int)Q, (int)F1);
+    return ok();
+}
+
+int covest_capon_spectrum(const void *R, int64_t count, int64_t P, int64_t Q, int64_t F1, int64_t F2, double *S,
+                          void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (count < 0 || P < 1 || Q < 1 || F1 < 1 || F2 < 1 || F1 > kCaponMaxGrid || F2 > kCaponMaxGrid)
+        return fail(COVEST_ERR_SHAPE, "need count >= 0, P, Q >= 1 and 1 <= F1, F2 <= %d", kCaponMaxGrid);
+    if (P * Q > kCaponMaxPQ) return fail(COVEST_ERR_UNSUPPORTED, "the spectrum supports PQ <= %d", kCaponMaxPQ);
+    if (count > INT32_MAX) return fail(COVEST_ERR_SHAPE, "count must be below 2^31");
+    if (count == 0) return ok();
+    if (!R || !S || !ws) return fail(COVEST_ERR_INVALID_ARG, "need R, S and ws");
+    const int n = (int)(P * Q);
+    const size_t per = capon_ws_per_matrix(n, (int)Q, (int)F1);
+    if (ws_bytes < (size_t)count * per)
+        return fail(COVEST_ERR_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, (size_t)count * per);
+    CaponArgs ca{};
+    ca.R = static_cast<const double2 *>(R);
+    ca.S = S;
+    ca.X = static_cast<double2 *>(ws);
+    ca.T = reinterpret_cast<double2 *>(static_cast<char *>(ws) + (size_t)count * 16 * n * n);
+    ca.n = n;
+    ca.P = (int)P;
+    ca.Q = (int)Q;
+    ca.F1 = (int)F1;
+    ca.F2 = (int)F2;
+    HIP_TRY(timed("capon", stream, [&] { return launch_capon(ca, (int)count, stream); }));
+    return finish_call(stream);
 }
 
 int covest_forward_batched(covest_plan *plan, hipStream_t stream)
