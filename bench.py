@@ -233,8 +233,33 @@ def _apertures(covest, synth, torch, dev, reps):
                         "fp64_roof_ms": 8.0 * um / (FP64_PEAK_TFLOPS * 1e12) * 1e3,
                         "r_write_gb_s": n_ap * (Pa * Qa) ** 2 * 16 / dt / 1e9, "plan_s": t_plan}
     print(f"[bench] apertures: {dt * 1e3:.3f} ms per image ({n_ap} matrices)", file=sys.stderr, flush=True)
+    # the consumer of R: the minimum-variance (Capon) spectrum of every aperture on a 64 x 64 grid
+    F = 64
+    R = plan.outputs
+    ws = torch.empty(covest_capon_ws(covest, n_ap, Pa, Qa, F), dtype=torch.uint8, device=dev)
+    S = covest.covest_capon_spectrum(R, Pa, Qa, F, F, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S = covest.covest_capon_spectrum(R, Pa, Qa, F, F, workspace=ws)
+    torch.cuda.synchronize()
+    dc = (time.perf_counter() - t0) / reps
+    n = Pa * Qa
+    flops = n_ap * 8.0 * (n ** 3 / 3 + n ** 3)   # Cholesky, then the two triangular solves for R^-1
+    out["apertures"]["capon"] = {"grid": f"{F}x{F}", "ms_per_image": dc * 1e3, "spectra_per_s": n_ap / dc,
+                                 "gflops_algorithmic": flops / dc / 1e9,
+                                 "fp64_roof_ms": flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3}
+    print(f"[bench] apertures: Capon spectra {dc * 1e3:.3f} ms per image", file=sys.stderr, flush=True)
+    del S, ws
     plan.close()
     return out
+
+
+def covest_capon_ws(covest, count, P, Q, F1):
+    import ctypes
+    n = ctypes.c_size_t(0)
+    covest._check(covest.lib().covest_capon_workspace_size(count, P, Q, F1, ctypes.byref(n)))
+    return int(n.value)
 
 
 def _adjoint(covest, synth, torch, dev):

@@ -1220,8 +1220,7 @@ int covest_capon_spectrum(const void *R, int64_t count, int64_t P, int64_t Q, in
     CaponArgs ca{};
     ca.R = static_cast<const double2 *>(R);
     ca.S = S;
-    ca.X = static_cast<double2 *>(ws);
-    ca.T = reinterpret_cast<double2 *>(static_cast<char *>(ws) + (size_t)count * 16 * n * n);
+    ca.T = static_cast<double2 *>(ws);
     ca.n = n;
     ca.P = (int)P;
     ca.Q = (int)Q;

@@ -10,14 +10,15 @@
 // (Sec. 3.1) -- and the spectrum over a grid of (w1, w2) is a separable 2-D
 // DFT of (2P-1) x (2Q-1) lag sums.
 //
-// One workgroup per matrix (n = PQ <= 128):
+// One workgroup per matrix (n = PQ <= 128), everything but the DFT in LDS:
 //   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2);
 //   2. Cholesky R = L L^H in place (right-looking, FP64);
-//   3. R^{-1} = L^{-H} L^{-1}: thread c solves L x = e_c, then L^H y = x, for
-//      column c, in the workspace; every thread walks the same rows, so the
-//      workspace reads coalesce and the LDS reads of L are broadcasts;
-//   4. the lag sums of R^{-1} into LDS (over the factor's space);
-//   5. T[f1][dj] = sum_di lag[di][dj] e^{-i w1 di}, then
+//   3. W = L^{-1} in place, column j from n-1 down to 0: with the trailing
+//      block already inverted, W[i][j] = -(1/L[j][j]) sum_{m=j+1..i} W[i][m] L[m][j]
+//      (column j of L is copied aside first);
+//   4. the lag sums of R^{-1} = W^H W, whose entry (k1, k2) is
+//      sum_{r >= max(k1,k2)} conj(W[r][k1]) W[r][k2];
+//   5. T[f1][dj] = sum_di lag[di][dj] e^{-i w1 di} (workspace), then
 //      S[f1][f2] = 1 / Re(sum_dj T[f1][dj] e^{-i w2 dj}).
 // A matrix that is not numerically positive definite (a pivot <= 0 or NaN)
 // gets an all-NaN spectrum.
@@ -29,9 +30,18 @@ namespace covest {
 
 namespace {
 
+constexpr int kCT = 512;   // threads per workgroup (the LDS allows one workgroup per CU)
+
 __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 
-__global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
+// Sum of v over the 4 lanes of a quad, in a fixed order (every lane gets it).
+__device__ __forceinline__ double quad_sum(double v)
+{
+    v += __shfl_xor(v, 1);
+    return v + __shfl_xor(v, 2);
+}
+
+__global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
 {
     extern __shared__ double2 Lp[];
     __shared__ int s_bad;
@@ -39,12 +49,11 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
     const int tid = threadIdx.x;
     const size_t mat = blockIdx.x;
     const double2 *R = ca.R + mat * n * n;
-    double2 *X = ca.X + mat * n * n;
     double2 *T = ca.T + mat * (size_t)F1 * (2 * Q - 1);
     double *S = ca.S + mat * (size_t)F1 * F2;
 
     // 1. lower triangle of R
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += kCT) {
         const int i = e / n, k = e - i * n;
         if (k <= i) Lp[tri(i) + k] = R[e];
     }
@@ -61,7 +70,7 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
             if (!(d > 0.0)) s_bad = 1;
         }
         const double inv = 1.0 / s;
-        for (int i = j + 1 + tid; i < n; i += 256) {
+        for (int i = j + 1 + tid; i < n; i += kCT) {
             double2 v = Lp[tri(i) + j];
             v.x *= inv;
             v.y *= inv;
@@ -70,7 +79,7 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
         __syncthreads();
         // trailing update: L[i][k] -= L[i][j] conj(L[k][j]) for j < k <= i
         const int m = n - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
+        for (int e = tid; e < m * m; e += kCT) {
             const int ii = e / m, kk = e - ii * m;
             if (kk <= ii) {
                 const int i = j + 1 + ii, k = j + 1 + kk;
@@ -85,50 +94,56 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
     }
     const bool bad = s_bad != 0;
 
-    // 3. R^{-1}, column c per thread
+    // 3. W = L^{-1} in place
+    const int nq = 2 * Q - 1, nl = (2 * P - 1) * nq;
+    double2 *col = Lp + tri(n);   // column j of L
+    double2 *lag = col + n;       // the lag sums
     if (!bad) {
-        for (int c = tid; c < n; c += 256) {
-            for (int k = 0; k < n; ++k) {   // L x = e_c
-                double sx = k == c ? 1.0 : 0.0, sy = 0.0;
-                const double2 *row = Lp + tri(k);
-                for (int m = 0; m < k; ++m) {
-                    const double2 l = row[m], x = X[(size_t)m * n + c];
-                    sx -= l.x * x.x - l.y * x.y;
-                    sy -= l.x * x.y + l.y * x.x;
+        for (int j = n - 1; j >= 0; --j) {
+            for (int i = j + 1 + tid; i < n; i += kCT) col[i] = Lp[tri(i) + j];
+            __syncthreads();   // also orders the previous step's pivot write
+            const double wjj = 1.0 / Lp[tri(j) + j].x;
+            // a quad per row: lane q of the quad takes m = j+1+q, j+5+q, ...
+            const int q = tid & 3;
+            for (int i = j + 1 + (tid >> 2); i < n; i += kCT / 4) {
+                const double2 *wrow = Lp + tri(i);
+                double sx = 0.0, sy = 0.0;
+#pragma unroll 4
+                for (int m = j + 1 + q; m <= i; m += 4) {
+                    const double2 w = wrow[m], l = col[m];
+                    sx += w.x * l.x - w.y * l.y;
+                    sy += w.x * l.y + w.y * l.x;
                 }
-                const double dinv = 1.0 / row[k].x;
-                X[(size_t)k * n + c] = make_double2(sx * dinv, sy * dinv);
+                sx = quad_sum(sx);
+                sy = quad_sum(sy);
+                if (q == 0) Lp[tri(i) + j] = make_double2(-wjj * sx, -wjj * sy);
             }
-            for (int k = n - 1; k >= 0; --k) {   // L^H y = x
-                const double2 xk = X[(size_t)k * n + c];
-                double sx = xk.x, sy = xk.y;
-                for (int m = k + 1; m < n; ++m) {
-                    const double2 l = Lp[tri(m) + k], y = X[(size_t)m * n + c];   // conj(l) * y
-                    sx -= l.x * y.x + l.y * y.y;
-                    sy -= l.x * y.y - l.y * y.x;
-                }
-                const double dinv = 1.0 / Lp[tri(k) + k].x;
-                X[(size_t)k * n + c] = make_double2(sx * dinv, sy * dinv);
-            }
+            __syncthreads();
+            if (tid == 0) Lp[tri(j) + j] = make_double2(wjj, 0.0);
         }
     }
-    __syncthreads();   // the solves' writes are visible to the workgroup; L is no longer needed
+    __syncthreads();
 
-    // 4. lag sums of R^{-1}: lag l = (di + P-1) * (2Q-1) + (dj + Q-1)
-    const int nq = 2 * Q - 1, nl = (2 * P - 1) * nq;
-    double2 *lag = Lp;
+    // 4. lag sums of R^{-1} = W^H W: lag l = (di + P-1) * (2Q-1) + (dj + Q-1)
     if (!bad) {
-        for (int l = tid; l < nl; l += 256) {
+        // a quad per lag: lane q of the quad takes rows r = r0+q, r0+4+q, ...
+        const int q = tid & 3;
+        for (int l = tid >> 2; l < nl; l += kCT / 4) {
             const int di = l / nq - (P - 1), dj = l - (l / nq) * nq - (Q - 1);
             double sx = 0.0, sy = 0.0;
             for (int j2 = max(0, -dj); j2 < Q - max(0, dj); ++j2)
                 for (int i2 = max(0, -di); i2 < P - max(0, di); ++i2) {
                     const int k2 = i2 + P * j2, k1 = (i2 + di) + P * (j2 + dj);
-                    const double2 v = X[(size_t)k1 * n + k2];
-                    sx += v.x;
-                    sy += v.y;
+#pragma unroll 4
+                    for (int r = max(k1, k2) + q; r < n; r += 4) {
+                        const double2 a = Lp[tri(r) + k1], b = Lp[tri(r) + k2];   // conj(a) * b
+                        sx += a.x * b.x + a.y * b.y;
+                        sy += a.x * b.y - a.y * b.x;
+                    }
                 }
-            lag[l] = make_double2(sx, sy);
+            sx = quad_sum(sx);
+            sy = quad_sum(sy);
+            if (q == 0) lag[l] = make_double2(sx, sy);
         }
     }
     __syncthreads();
@@ -137,7 +152,7 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
     const double two_pi = 6.283185307179586476925286766559;
     const double pi = 3.14159265358979323846264338328;
     if (!bad) {
-        for (int e = tid; e < F1 * nq; e += 256) {
+        for (int e = tid; e < F1 * nq; e += kCT) {
             const int f1 = e / nq, q = e - f1 * nq;
             const double w1 = -pi + two_pi * f1 / F1;
             double sx = 0.0, sy = 0.0;
@@ -152,7 +167,7 @@ __global__ void __launch_bounds__(256) capon_kernel(CaponArgs ca)
         }
     }
     __syncthreads();
-    for (int e = tid; e < F1 * F2; e += 256) {
+    for (int e = tid; e < F1 * F2; e += kCT) {
         if (bad) {
             S[e] = __builtin_nan("");
             continue;
@@ -178,7 +193,7 @@ hipError_t launch_capon(const CaponArgs &ca, int count, hipStream_t stream)
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (attr != hipSuccess) return attr;
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(capon_kernel, dim3(count), dim3(256), capon_lds_bytes(ca.n, ca.P, ca.Q), stream, ca);
+    hipLaunchKernelGGL(capon_kernel, dim3(count), dim3(kCT), capon_lds_bytes(ca.n, ca.P, ca.Q), stream, ca);
     return hipGetLastError();
 }
 

@@ -95,7 +95,7 @@ def test_capon_argument_errors_before_device_use():
     assert L.covest_capon_workspace_size(4, 10, 10, 64, None) == cv.ERR_INVALID_ARG
     assert L.covest_capon_workspace_size(4, 10, 10, 64, ctypes.byref(n)) == cv.OK
     need = n.value
-    assert need == 4 * 16 * (100 * 100 + 64 * 19)
+    assert need == 4 * 16 * 64 * 19
     fake = ctypes.c_void_p(256)
     assert L.covest_capon_spectrum(fake, 4, 10, 10, 64, 64, fake, fake, need - 1, None) == cv.ERR_WORKSPACE
     assert L.covest_capon_spectrum(None, 4, 10, 10, 64, 64, fake, fake, need, None) == cv.ERR_INVALID_ARG
