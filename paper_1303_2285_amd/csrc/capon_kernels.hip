@@ -12,7 +12,8 @@
 //
 // One workgroup per matrix (n = PQ <= 128), everything but the DFT in LDS:
 //   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2);
-//   2. Cholesky R = L L^H in place (right-looking, FP64);
+//   2. Cholesky R = L L^H in place (right-looking, FP64, one barrier per
+//      column: the column's scaling is deferred to one pass at the end);
 //   3. W = L^{-1} in place, column j from n-1 down to 0: with the trailing
 //      block already inverted, W[i][j] = -(1/L[j][j]) sum_{m=j+1..i} W[i][m] L[m][j]
 //      (column j of L is copied aside first);
@@ -60,39 +61,44 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
     if (tid == 0) s_bad = 0;
     __syncthreads();
 
-    // 2. Cholesky, column j at a time
+    // 2. Cholesky, column j at a time, the column's scaling deferred: column j
+    // keeps a[i][j] = L[i][j] * L[j][j] and the update divides by the pivot
+    // d = L[j][j]^2, so a step needs one barrier; the pivots' square roots go
+    // to piv and the factor is rescaled once at the end.
+    double *piv = reinterpret_cast<double *>(Lp + tri(n));   // n doubles, in the column buffer
     for (int j = 0; j < n; ++j) {
-        const double d = Lp[tri(j) + j].x;
-        const double s = sqrt(d);
-        __syncthreads();   // every thread has read the pivot
+        const double d = Lp[tri(j) + j].x;   // final since the previous step's barrier
         if (tid == 0) {
-            Lp[tri(j) + j] = make_double2(s, 0.0);
+            piv[j] = sqrt(d);
             if (!(d > 0.0)) s_bad = 1;
         }
-        const double inv = 1.0 / s;
-        for (int i = j + 1 + tid; i < n; i += kCT) {
-            double2 v = Lp[tri(i) + j];
-            v.x *= inv;
-            v.y *= inv;
-            Lp[tri(i) + j] = v;
-        }
-        __syncthreads();
-        // trailing update: L[i][k] -= L[i][j] conj(L[k][j]) for j < k <= i
+        const double invd = 1.0 / d;
+        // trailing update: A[i][k] -= a[i][j] conj(a[k][j]) / d for j < k <= i
         const int m = n - j - 1;
-        for (int e = tid; e < m * m; e += kCT) {
-            const int ii = e / m, kk = e - ii * m;
-            if (kk <= ii) {
-                const int i = j + 1 + ii, k = j + 1 + kk;
-                const double2 a = Lp[tri(i) + j], b = Lp[tri(k) + j];
+        for (int ii = tid >> 4; ii < m; ii += kCT >> 4) {
+            const int i = j + 1 + ii;
+            const double2 a = Lp[tri(i) + j];
+            for (int kk = tid & 15; kk <= ii; kk += 16) {
+                const int k = j + 1 + kk;
+                const double2 b = Lp[tri(k) + j];
                 double2 t = Lp[tri(i) + k];
-                t.x -= a.x * b.x + a.y * b.y;
-                t.y -= a.y * b.x - a.x * b.y;
+                t.x -= (a.x * b.x + a.y * b.y) * invd;
+                t.y -= (a.y * b.x - a.x * b.y) * invd;
                 Lp[tri(i) + k] = t;
             }
         }
         __syncthreads();
     }
     const bool bad = s_bad != 0;
+    // rescale: L[i][j] = a[i][j] / piv[j], L[j][j] = piv[j]
+    for (int i = tid >> 4; i < n; i += kCT >> 4)
+        for (int j = tid & 15; j <= i; j += 16) {
+            const double sj = piv[j];
+            double2 v = Lp[tri(i) + j];
+            v = j == i ? make_double2(sj, 0.0) : make_double2(v.x / sj, v.y / sj);
+            Lp[tri(i) + j] = v;
+        }
+    __syncthreads();
 
     // 3. W = L^{-1} in place
     const int nq = 2 * Q - 1, nl = (2 * P - 1) * nq;
@@ -134,11 +140,13 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
             for (int j2 = max(0, -dj); j2 < Q - max(0, dj); ++j2)
                 for (int i2 = max(0, -di); i2 < P - max(0, di); ++i2) {
                     const int k2 = i2 + P * j2, k1 = (i2 + di) + P * (j2 + dj);
+                    int r = max(k1, k2) + q, base = tri(r);
 #pragma unroll 4
-                    for (int r = max(k1, k2) + q; r < n; r += 4) {
-                        const double2 a = Lp[tri(r) + k1], b = Lp[tri(r) + k2];   // conj(a) * b
+                    for (; r < n; r += 4) {   // tri(r + 4) = tri(r) + 4r + 10
+                        const double2 a = Lp[base + k1], b = Lp[base + k2];   // conj(a) * b
                         sx += a.x * b.x + a.y * b.y;
                         sy += a.x * b.y - a.y * b.x;
+                        base += 4 * r + 10;
                     }
                 }
             sx = quad_sum(sx);
