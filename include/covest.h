@@ -219,8 +219,9 @@ int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *
  * S being count x F1 x F2 doubles (device).  Cholesky factor in FP64, R^{-1}
  * from two triangular solves, its sums along the lags (i1 - i2, j1 - j2) and a
  * separable 2-D DFT of those sums (the quadratic form depends on R^{-1} only
- * through them).  Limits: PQ <= 128 (COVEST_ERR_UNSUPPORTED), 1 <= F1, F2 <=
- * 4096 (COVEST_ERR_SHAPE).  ws holds covest_capon_workspace_size() bytes
+ * through them).  Limits: PQ <= 256 (COVEST_ERR_UNSUPPORTED; above PQ = 128
+ * the factor lives in the workspace, not in LDS, and the call is slower),
+ * 1 <= F1, F2 <= 4096 (COVEST_ERR_SHAPE).  ws holds covest_capon_workspace_size() bytes
  * (COVEST_ERR_WORKSPACE if smaller).  A matrix that is not numerically positive
  * definite (a Cholesky pivot <= 0 or NaN) gets an all-NaN spectrum. */
 int covest_capon_workspace_size(int64_t count, int64_t P, int64_t Q, int64_t F1, size_t *bytes);

@@ -1221,6 +1221,7 @@ int covest_capon_spectrum(const void *R, int64_t count, int64_t P, int64_t Q, in
     ca.R = static_cast<const double2 *>(R);
     ca.S = S;
     ca.T = static_cast<double2 *>(ws);
+    ca.F = reinterpret_cast<double2 *>(static_cast<char *>(ws) + (size_t)count * capon_t_bytes((int)Q, (int)F1));
     ca.n = n;
     ca.P = (int)P;
     ca.Q = (int)Q;

@@ -10,7 +10,8 @@
 // (Sec. 3.1) -- and the spectrum over a grid of (w1, w2) is a separable 2-D
 // DFT of (2P-1) x (2Q-1) lag sums.
 //
-// One workgroup per matrix (n = PQ <= 128), everything but the DFT in LDS:
+// One workgroup per matrix (n = PQ <= 256); for n <= 128 everything but the
+// DFT lives in LDS, above that the packed factor lives in the workspace:
 //   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2);
 //   2. Cholesky R = L L^H in place (right-looking, FP64, one barrier per
 //      column: the column's scaling is deferred to one pass at the end);
@@ -42,9 +43,12 @@ __device__ __forceinline__ double quad_sum(double v)
     return v + __shfl_xor(v, 2);
 }
 
+// GF: the packed factor lives in the workspace (global memory, L2-resident)
+// instead of LDS, for PQ above what one CU's LDS holds; the code is the same.
+template <bool GF>
 __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
 {
-    extern __shared__ double2 Lp[];
+    extern __shared__ double2 sh[];
     __shared__ int s_bad;
     const int n = ca.n, P = ca.P, Q = ca.Q, F1 = ca.F1, F2 = ca.F2;
     const int tid = threadIdx.x;
@@ -52,6 +56,8 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
     const double2 *R = ca.R + mat * n * n;
     double2 *T = ca.T + mat * (size_t)F1 * (2 * Q - 1);
     double *S = ca.S + mat * (size_t)F1 * F2;
+    double2 *Lp = GF ? ca.F + mat * (size_t)tri(n) : sh;
+    double2 *const colbuf = GF ? sh : sh + tri(n);   // n entries, then the lag sums
 
     // 1. lower triangle of R
     for (int e = tid; e < n * n; e += kCT) {
@@ -65,7 +71,7 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
     // keeps a[i][j] = L[i][j] * L[j][j] and the update divides by the pivot
     // d = L[j][j]^2, so a step needs one barrier; the pivots' square roots go
     // to piv and the factor is rescaled once at the end.
-    double *piv = reinterpret_cast<double *>(Lp + tri(n));   // n doubles, in the column buffer
+    double *piv = reinterpret_cast<double *>(colbuf);   // n doubles, in the column buffer
     for (int j = 0; j < n; ++j) {
         const double d = Lp[tri(j) + j].x;   // final since the previous step's barrier
         if (tid == 0) {
@@ -102,8 +108,8 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
 
     // 3. W = L^{-1} in place
     const int nq = 2 * Q - 1, nl = (2 * P - 1) * nq;
-    double2 *col = Lp + tri(n);   // column j of L
-    double2 *lag = col + n;       // the lag sums
+    double2 *col = colbuf;        // column j of L
+    double2 *lag = colbuf + n;    // the lag sums
     if (!bad) {
         for (int j = n - 1; j >= 0; --j) {
             for (int i = j + 1 + tid; i < n; i += kCT) col[i] = Lp[tri(i) + j];
@@ -197,11 +203,16 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
 
 hipError_t launch_capon(const CaponArgs &ca, int count, hipStream_t stream)
 {
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&capon_kernel),
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&capon_kernel<false>),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (attr != hipSuccess) return attr;
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(capon_kernel, dim3(count), dim3(kCT), capon_lds_bytes(ca.n, ca.P, ca.Q), stream, ca);
+    if (capon_factor_in_lds(ca.n))
+        hipLaunchKernelGGL(capon_kernel<false>, dim3(count), dim3(kCT), capon_lds_bytes(ca.n, ca.P, ca.Q), stream,
+                           ca);
+    else
+        hipLaunchKernelGGL(capon_kernel<true>, dim3(count), dim3(kCT), capon_lds_bytes(ca.n, ca.P, ca.Q), stream,
+                           ca);
     return hipGetLastError();
 }
 

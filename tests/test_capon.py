@@ -90,7 +90,9 @@ def test_capon_argument_errors_before_device_use():
     from paper_1303_2285_amd import covest as cv
     L = cv.lib()
     n = ctypes.c_size_t(0)
-    assert L.covest_capon_workspace_size(4, 12, 11, 64, ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    assert L.covest_capon_workspace_size(4, 17, 16, 64, ctypes.byref(n)) == cv.ERR_UNSUPPORTED
+    assert L.covest_capon_workspace_size(1, 16, 16, 64, ctypes.byref(n)) == cv.OK
+    assert n.value == 16 * (64 * 31 + 256 * 257 // 2)   # the factor in the workspace above PQ = 128
     assert L.covest_capon_workspace_size(4, 10, 10, 0, ctypes.byref(n)) == cv.ERR_SHAPE
     assert L.covest_capon_workspace_size(4, 10, 10, 64, None) == cv.ERR_INVALID_ARG
     assert L.covest_capon_workspace_size(4, 10, 10, 64, ctypes.byref(n)) == cv.OK
@@ -100,7 +102,8 @@ def test_capon_argument_errors_before_device_use():
     assert L.covest_capon_spectrum(fake, 4, 10, 10, 64, 64, fake, fake, need - 1, None) == cv.ERR_WORKSPACE
     assert L.covest_capon_spectrum(None, 4, 10, 10, 64, 64, fake, fake, need, None) == cv.ERR_INVALID_ARG
     assert L.covest_capon_spectrum(fake, 4, 10, 10, 64, 5000, fake, fake, need, None) == cv.ERR_SHAPE
-    assert L.covest_capon_spectrum(fake, 4, 16, 16, 64, 64, fake, fake, need, None) == cv.ERR_UNSUPPORTED
+    assert L.covest_capon_spectrum(fake, 4, 16, 17, 64, 64, fake, fake, need, None) == cv.ERR_UNSUPPORTED
+    assert L.covest_capon_spectrum(fake, 4, 16, 16, 64, 64, fake, fake, need, None) == cv.ERR_WORKSPACE
     assert L.covest_capon_spectrum(None, 0, 10, 10, 64, 64, None, None, 0, None) == cv.OK
 
 
@@ -122,7 +125,8 @@ def cv():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", [(1, 1, 8, 8), (3, 4, 16, 12), (8, 8, 64, 64), (10, 10, 64, 48),
-                                   (16, 8, 32, 32), (11, 11, 40, 40), (2, 64, 16, 64), (7, 1, 33, 1)],
+                                   (16, 8, 32, 32), (11, 11, 40, 40), (2, 64, 16, 64), (7, 1, 33, 1),
+                                   (12, 11, 24, 24), (16, 16, 32, 32), (4, 64, 8, 32)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_gpu_random_hpd(cv, tdev, oracle_mod, shape):
     torch, dev = tdev
@@ -168,3 +172,18 @@ def test_gpu_aperture_pipeline(cv, tdev, oracle_mod):
             ref = oracle_mod.capon(oracle_mod.forward(sub, P, Q, threads=oracle_mod.max_threads()), P, Q, F, F)
             assert np.max(np.abs(S[a, b] - ref) / np.abs(ref)) <= 1e-9, (a, b)
             peak_checks(S[a, b], w, F, F)
+
+
+@pytest.mark.gpu
+def test_gpu_three_exponentials_16x16(cv, tdev):
+    """The 256 x 256 input of three exponentials 10 dB above the noise with a
+    16 x 16 window (PQ = 256, the factor in the workspace): R on the GPU, its
+    spectrum on the GPU, peaks at the three generated frequencies."""
+    torch, dev = tdev
+    A, P, Q = synth.config_input("medium")
+    w, _ = synth.exponential_params(2, 3)
+    _note("capon 256x256 three exponentials, 16x16 window")
+    R = cv.covest_forward(torch.from_numpy(A).to(dev), P, Q)
+    S = cv.covest_capon_spectrum(R, P, Q, 128, 128).cpu().numpy()
+    peak_checks(S, w, 128, 128)
+
