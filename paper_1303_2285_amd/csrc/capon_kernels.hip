@@ -21,7 +21,8 @@
 //   4. the lag sums of R^{-1} = W^H W, whose entry (k1, k2) is
 //      sum_{r >= max(k1,k2)} conj(W[r][k1]) W[r][k2];
 //   5. T[f1][dj] = sum_di lag[di][dj] e^{-i w1 di} (workspace), then
-//      S[f1][f2] = 1 / Re(sum_dj T[f1][dj] e^{-i w2 dj}).
+//      S[f1][f2] = 1 / Re(sum_dj T[f1][dj] e^{-i w2 dj}), the twiddles of each
+//      sum by a recurrence from its first (two sincos per output).
 // A matrix that is not numerically positive definite (a pivot <= 0 or NaN)
 // gets an all-NaN spectrum.
 #include "capon_internal.hpp"
@@ -169,13 +170,18 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
         for (int e = tid; e < F1 * nq; e += kCT) {
             const int f1 = e / nq, q = e - f1 * nq;
             const double w1 = -pi + two_pi * f1 / F1;
+            // twiddles e^{-i w1 (p - (P-1))} by a recurrence from p = 0
+            double tr, ti, sr, si;
+            sincos(w1 * (P - 1), &ti, &tr);
+            sincos(-w1, &si, &sr);
             double sx = 0.0, sy = 0.0;
             for (int p = 0; p < 2 * P - 1; ++p) {
-                double sn, cs;
-                sincos(-w1 * (p - (P - 1)), &sn, &cs);
                 const double2 v = lag[p * nq + q];
-                sx += v.x * cs - v.y * sn;
-                sy += v.x * sn + v.y * cs;
+                sx += v.x * tr - v.y * ti;
+                sy += v.x * ti + v.y * tr;
+                const double nr = tr * sr - ti * si;
+                ti = tr * si + ti * sr;
+                tr = nr;
             }
             T[e] = make_double2(sx, sy);
         }
@@ -188,12 +194,16 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
         }
         const int f1 = e / F2, f2 = e - f1 * F2;
         const double w2 = -pi + two_pi * f2 / F2;
+        double tr, ti, sr, si;   // e^{-i w2 (q - (Q-1))} by a recurrence from q = 0
+        sincos(w2 * (Q - 1), &ti, &tr);
+        sincos(-w2, &si, &sr);
         double re = 0.0;
         for (int q = 0; q < nq; ++q) {
-            double sn, cs;
-            sincos(-w2 * (q - (Q - 1)), &sn, &cs);
             const double2 t = T[f1 * nq + q];
-            re += t.x * cs - t.y * sn;
+            re += t.x * tr - t.y * ti;
+            const double nr = tr * sr - ti * si;
+            ti = tr * si + ti * sr;
+            tr = nr;
         }
         S[e] = 1.0 / re;
     }
