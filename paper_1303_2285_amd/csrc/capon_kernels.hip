@@ -19,7 +19,8 @@
 //      block already inverted, W[i][j] = -(1/L[j][j]) sum_{m=j+1..i} W[i][m] L[m][j]
 //      (column j of L is copied aside first);
 //   4. the lag sums of R^{-1} = W^H W, whose entry (k1, k2) is
-//      sum_{r >= max(k1,k2)} conj(W[r][k1]) W[r][k2];
+//      sum_{r >= max(k1,k2)} conj(W[r][k1]) W[r][k2] (half of the lags: the
+//      others are their conjugates);
 //   5. T[f1][dj] = sum_di lag[di][dj] e^{-i w1 di} (workspace), then
 //      S[f1][f2] = 1 / Re(sum_dj T[f1][dj] e^{-i w2 dj}), the twiddles of each
 //      sum by a recurrence from its first (two sincos per output).
@@ -139,9 +140,12 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
 
     // 4. lag sums of R^{-1} = W^H W: lag l = (di + P-1) * (2Q-1) + (dj + Q-1)
     if (!bad) {
-        // a quad per lag: lane q of the quad takes rows r = r0+q, r0+4+q, ...
-        const int q = tid & 3;
-        for (int l = tid >> 2; l < nl; l += kCT / 4) {
+        // R^{-1} is Hermitian, so the sum along -(di, dj) is the conjugate of
+        // the sum along (di, dj): only lags from the centre lc = (P-1)(2Q-1) +
+        // (Q-1) up are summed, each also written conjugated to 2 lc - l.
+        // A quad per lag: lane q of the quad takes rows r = r0+q, r0+4+q, ...
+        const int q = tid & 3, lc = (P - 1) * nq + (Q - 1);
+        for (int l = lc + (tid >> 2); l < nl; l += kCT / 4) {
             const int di = l / nq - (P - 1), dj = l - (l / nq) * nq - (Q - 1);
             double sx = 0.0, sy = 0.0;
             for (int j2 = max(0, -dj); j2 < Q - max(0, dj); ++j2)
@@ -158,7 +162,10 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
                 }
             sx = quad_sum(sx);
             sy = quad_sum(sy);
-            if (q == 0) lag[l] = make_double2(sx, sy);
+            if (q == 0) {
+                lag[l] = make_double2(sx, sy);
+                if (l != lc) lag[2 * lc - l] = make_double2(sx, -sy);
+            }
         }
     }
     __syncthreads();
