@@ -14,7 +14,7 @@ constexpr int kCaponLdsPQ = 128;     // up to this PQ the packed factor lives in
 constexpr int kCaponMaxGrid = 4096;  // F1, F2 at most
 
 // One workgroup per matrix.  LDS: the packed factor (n(n+1)/2, n <= 128
-// only), one column (n) and the lag sums ((2P-1)(2Q-1)), complex128.
+// only), two columns (2n) and the lag sums ((2P-1)(2Q-1)), complex128.
 // Workspace per matrix: T (F1 x (2Q-1), the first DFT pass) and, for n > 128,
 // the packed factor, complex128.
 struct CaponArgs {
@@ -30,7 +30,7 @@ inline bool capon_factor_in_lds(int n) { return n <= kCaponLdsPQ; }
 inline size_t capon_lds_bytes(int n, int P, int Q)
 {
     const size_t tri = capon_factor_in_lds(n) ? (size_t)n * (n + 1) / 2 : 0;
-    return 16 * (tri + (size_t)n + (size_t)(2 * P - 1) * (2 * Q - 1));
+    return 16 * (tri + 2 * (size_t)n + (size_t)(2 * P - 1) * (2 * Q - 1));
 }
 
 inline size_t capon_t_bytes(int Q, int F1) { return 16 * (size_t)F1 * (2 * Q - 1); }

@@ -15,9 +15,9 @@
 //   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2);
 //   2. Cholesky R = L L^H in place (right-looking, FP64, one barrier per
 //      column: the column's scaling is deferred to one pass at the end);
-//   3. W = L^{-1} in place, column j from n-1 down to 0: with the trailing
-//      block already inverted, W[i][j] = -(1/L[j][j]) sum_{m=j+1..i} W[i][m] L[m][j]
-//      (column j of L is copied aside first);
+//   3. W = L^{-1} in place, columns from n-1 down to 0, two per step: with
+//      the trailing block already inverted, W[i][j] = -(1/L[j][j]) sum_{m=j+1..i}
+//      W[i][m] L[m][j] (the columns of L are copied aside first);
 //   4. the lag sums of R^{-1} = W^H W, whose entry (k1, k2) is
 //      sum_{r >= max(k1,k2)} conj(W[r][k1]) W[r][k2] (half of the lags: the
 //      others are their conjugates);
@@ -108,32 +108,74 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
         }
     __syncthreads();
 
-    // 3. W = L^{-1} in place
+    // 3. W = L^{-1} in place, two columns (j, j-1) per step: for i > j
+    //      W[i][j]   = -(1/L[j][j])     sum_{m=j+1..i} W[i][m] L[m][j]
+    //      W[i][j-1] = -(1/L[j-1][j-1]) (W[i][j] L[j][j-1] + sum_{m=j+1..i} W[i][m] L[m][j-1])
+    // from one pass over row i of the inverted trailing block; W[j][j-1] =
+    // -(1/L[j-1][j-1]) W[j][j] L[j][j-1]; an odd n leaves column 0 alone.
     const int nq = 2 * Q - 1, nl = (2 * P - 1) * nq;
-    double2 *col = colbuf;        // column j of L
-    double2 *lag = colbuf + n;    // the lag sums
+    double2 *col = colbuf;           // column j of L
+    double2 *col2 = colbuf + n;      // column j-1 of L
+    double2 *lag = colbuf + 2 * n;   // the lag sums
     if (!bad) {
-        for (int j = n - 1; j >= 0; --j) {
+        const int q = tid & 3;
+        int j = n - 1;
+        for (; j >= 1; j -= 2) {
+            const int j1 = j - 1;
             for (int i = j + 1 + tid; i < n; i += kCT) col[i] = Lp[tri(i) + j];
-            __syncthreads();   // also orders the previous step's pivot write
-            const double wjj = 1.0 / Lp[tri(j) + j].x;
-            // a quad per row: lane q of the quad takes m = j+1+q, j+5+q, ...
-            const int q = tid & 3;
+            for (int i = j + tid; i < n; i += kCT) col2[i] = Lp[tri(i) + j1];
+            __syncthreads();   // also orders the previous step's diagonal writes
+            const double wjj = 1.0 / Lp[tri(j) + j].x, w11 = 1.0 / Lp[tri(j1) + j1].x;
+            const double2 ljj1 = col2[j];   // L[j][j-1]
             for (int i = j + 1 + (tid >> 2); i < n; i += kCT / 4) {
+                const double2 *wrow = Lp + tri(i);
+                double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll 4
+                for (int m = j + 1 + q; m <= i; m += 4) {
+                    const double2 w = wrow[m], l = col[m], l2 = col2[m];
+                    ax += w.x * l.x - w.y * l.y;
+                    ay += w.x * l.y + w.y * l.x;
+                    bx += w.x * l2.x - w.y * l2.y;
+                    by += w.x * l2.y + w.y * l2.x;
+                }
+                ax = quad_sum(ax);
+                ay = quad_sum(ay);
+                bx = quad_sum(bx);
+                by = quad_sum(by);
+                if (q == 0) {
+                    const double wx = -wjj * ax, wy = -wjj * ay;   // W[i][j]
+                    const double cx = wx * ljj1.x - wy * ljj1.y + bx;
+                    const double cy = wx * ljj1.y + wy * ljj1.x + by;
+                    Lp[tri(i) + j] = make_double2(wx, wy);
+                    Lp[tri(i) + j1] = make_double2(-w11 * cx, -w11 * cy);
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                Lp[tri(j) + j] = make_double2(wjj, 0.0);
+                Lp[tri(j) + j1] = make_double2(-w11 * wjj * ljj1.x, -w11 * wjj * ljj1.y);
+                Lp[tri(j1) + j1] = make_double2(w11, 0.0);
+            }
+        }
+        if (j == 0) {   // n odd: column 0
+            for (int i = 1 + tid; i < n; i += kCT) col[i] = Lp[tri(i)];
+            __syncthreads();
+            const double w00 = 1.0 / Lp[0].x;
+            for (int i = 1 + (tid >> 2); i < n; i += kCT / 4) {
                 const double2 *wrow = Lp + tri(i);
                 double sx = 0.0, sy = 0.0;
 #pragma unroll 4
-                for (int m = j + 1 + q; m <= i; m += 4) {
+                for (int m = 1 + q; m <= i; m += 4) {
                     const double2 w = wrow[m], l = col[m];
                     sx += w.x * l.x - w.y * l.y;
                     sy += w.x * l.y + w.y * l.x;
                 }
                 sx = quad_sum(sx);
                 sy = quad_sum(sy);
-                if (q == 0) Lp[tri(i) + j] = make_double2(-wjj * sx, -wjj * sy);
+                if (q == 0) Lp[tri(i)] = make_double2(-w00 * sx, -w00 * sy);
             }
             __syncthreads();
-            if (tid == 0) Lp[tri(j) + j] = make_double2(wjj, 0.0);
+            if (tid == 0) Lp[0] = make_double2(w00, 0.0);
         }
     }
     __syncthreads();
