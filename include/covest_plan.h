@@ -68,11 +68,21 @@ typedef struct {
 } covest_mfma_plan_info;
 
 /* Fills *out and, when non-null, the job rows (16 int32 each: inst, orient,
- * kind, out, line0, line_end, b0, kg0, b1, kg1, n_kg, pos_lo, pos_hi, k0, 0, 0)
+ * kind, out, line0, line_end, b0, kg0, b1, kg1, n_kg, pos_lo, pos_hi, k0, kin, 0;
+ * kin: the k-groups [0, kin) whose four positions all lie inside the line,
+ * whose first operand the kernel loads without a clamp)
  * and the finalize item rows (5 int32 each, as covest_plan_tables).
  * COVEST_ERR_UNSUPPORTED when the engine cannot run the shape. */
 int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
                          covest_mfma_plan_info *out, int32_t *jobs, int32_t *items);
+
+/* The engine COVEST_ENGINE_AUTO picks for one problem (batch = 0) or for a
+ * problem of a batched plan (batch = 1): *engine = COVEST_ENGINE_VECTOR or
+ * COVEST_ENGINE_MATRIX.  *fits = 1 when the matrix-core engine can run the
+ * shape at all (what COVEST_ENGINE_MATRIX accepts).  Host only; ignores the
+ * 2^31-element offset limit, which depends on lda. */
+int covest_engine_choice(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t batch, int32_t *engine,
+                         int32_t *fits);
 
 #ifdef __cplusplus
 }

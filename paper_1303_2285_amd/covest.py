@@ -125,6 +125,8 @@ SIGNATURES = {
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "covest_mfma_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
                                     ctypes.POINTER(covest_mfma_plan_info), ctypes.c_void_p, ctypes.c_void_p]),
+    "covest_engine_choice": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -497,3 +499,18 @@ def mfma_plan(N, M, P, Q, n_cu=256):
     _check(lib().covest_mfma_plan_get(N, M, P, Q, n_cu, ctypes.byref(info), jobs.ctypes.data,
                                       items.ctypes.data))
     return d, jobs, items
+
+
+def engine_choice(N, M, P, Q, batch=False):
+    """(engine AUTO picks: "vector" or "matrix", whether the matrix cores can run the shape)."""
+    e, f = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().covest_engine_choice(N, M, P, Q, 1 if batch else 0, ctypes.byref(e), ctypes.byref(f)))
+    return ("matrix" if e.value == ENGINES["matrix"] else "vector"), bool(f.value)
+
+
+def mfma_fits(N, M, P, Q) -> bool:
+    return engine_choice(N, M, P, Q)[1]
+
+
+def mfma_preferred(N, M, P, Q, batch=False) -> bool:
+    return engine_choice(N, M, P, Q, batch)[0] == "matrix"

@@ -1368,6 +1368,20 @@ int covest_timing_read(covest_timing_record *out, int cap)
 
 }  // extern "C"
 
+extern "C" int covest_engine_choice(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t batch, int32_t *engine,
+                                    int32_t *fits)
+{
+    if (!engine || !fits) return fail(COVEST_ERR_INVALID_ARG, "engine and fits must be non-null");
+    int st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
+    *fits = mfma_fits((int)N, (int)M, (int)P, (int)Q) ? 1 : 0;
+    *engine = mfma_preferred((int)N, (int)M, (int)P, (int)Q, batch != 0) ? COVEST_ENGINE_MATRIX
+                                                                         : COVEST_ENGINE_VECTOR;
+    return ok();
+}
+
 extern "C" int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
                                     covest_mfma_plan_info *out, int32_t *jobs, int32_t *items)
 {
@@ -1401,7 +1415,7 @@ extern "C" int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, 
             for (size_t k = 0; k < sp.mjobs.size(); ++k) {
                 const MJob &j = sp.mjobs[k];
                 const int32_t row[16] = {j.inst, j.orient, j.kind, j.out, j.line0, j.line_end, j.b0, j.kg0,
-                                         j.b1, j.kg1, j.n_kg, j.pos_lo, j.pos_hi, j.k0, 0, 0};
+                                         j.b1, j.kg1, j.n_kg, j.pos_lo, j.pos_hi, j.k0, j.kin, 0};
                 std::memcpy(jobs + 16 * k, row, sizeof(row));
             }
         }

@@ -147,7 +147,9 @@ struct MJob {
     int n_kg;            // k-groups per line
     int pos_lo, pos_hi;  // first-factor positions [pos_lo, pos_hi) on every line
     int k0;              // second-factor position of k-group 0, lane 0
-    int pad0, pad1;
+    int kin;             // k-groups [0, kin) have all 4 positions inside the line
+                         // (loaded unchecked); later ones are clamped to its end
+    int pad1;
 };
 
 // The problem descriptor travels in the kernel arguments, so that its fields

@@ -327,6 +327,15 @@ bool mfma_preferred(int N, int M, int P, int Q, bool batch)
     return !(fill < 0.3 && tiles >= 7);
 }
 
+// K-groups of 4 positions, the first at k0, that lie wholly inside a line of
+// npos positions (at most nkg).  Written with a guard, not as one truncating
+// division: for npos - k0 < 4 the count is 0, not 1.
+static int kgroups_inside(int npos, int k0, int nkg)
+{
+    if (npos - k0 < 4) return 0;
+    return std::min(nkg, (npos - k0 - 4) / 4 + 1);
+}
+
 ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units)
 {
     ShapePlan sp;
@@ -402,6 +411,7 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units)
             j.pos_lo = plo[o];
             j.pos_hi = phi[o];
             j.k0 = k0[o];
+            j.kin = kgroups_inside(o ? N : M, k0[o], nk);
             strips.push_back(j);
             smax = std::max(smax, j.kg1 - j.kg0);
         }
@@ -430,6 +440,7 @@ ShapePlan make_mfma_plan(int N, int M, int P, int Q, int n_cu, double job_units)
         b.pos_lo = plo[0];
         b.pos_hi = phi[0];
         b.k0 = k0[0];
+        b.kin = kgroups_inside(M, k0[0], nkg[0]);
         sp.mjobs.push_back(b);
         sp.job_cost.push_back((double)(u1 - u0));
     }

@@ -102,6 +102,8 @@ __device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const fl
 template <int MT, int NT, class Load>
 __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], Load load)
 {
+    // an empty range loads nothing (its first load would be k-group k_a - 1)
+    if (k_a >= k_b) return;
     constexpr int D = MT * NT >= 8 ? 1 : MT * NT >= 4 ? 2 : 4;
     float2 an[D][MT], xn[D][NT];
 #pragma unroll
@@ -130,6 +132,8 @@ __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT
 // clamps its positions in the one k-group that can pass row N-1.  The
 // line's own values (the second operand), zeroed outside [pos_lo, pos_hi),
 // are staged per wave in LDS, kMXCap of them at a time, and read from there.
+// The planner sets job.kin, the k-groups that need no clamp: 0 for a line of
+// fewer than 4 positions past k0.
 template <int MT, int NT, int OR>
 __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
 {
@@ -148,8 +152,8 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     const int npos = OR ? in.N : in.M;
     const int d1lo = OR ? 0 : -(in.P - 1);
     const int d2lo = OR ? -(in.P - 1) : 0;
-    // k-groups whose 4 positions all lie inside A
-    const int kin = (npos - 4 - job.k0) / 4 + 1;
+    // k-groups whose 4 positions all lie inside A (the planner counts them)
+    const int kin = job.kin;
 
     v4d acc[T][2];
 #pragma unroll
@@ -212,7 +216,8 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
                                 [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, aoff, an, xn); });
             if (kplain < kce) {
                 // the last k-group of a line can pass A's last position: clamp
-                // it (at most one k-group; orientation 0 never gets here)
+                // it (at most one k-group, the planner's kin is n_kg - 1 or
+                // n_kg; orientation 0 never gets here)
                 const int pos = job.k0 + 4 * kplain + kq;
                 uint32_t off[MT];
 #pragma unroll

@@ -148,3 +148,19 @@ def test_matrix_engine_low_fill_bit_exact(cv, torch_dev, oracle_mod, shape):
     R = run(cv, torch_dev, A, P, Q, engine="matrix")
     ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
     assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
+
+
+@pytest.mark.parametrize("shape", [(1, 9, 1, 4), (2, 7, 1, 4), (3, 7, 2, 4), (3, 200, 2, 64), (1, 127, 1, 64),
+                                   (2, 33, 1, 17)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("engine", ["auto", "matrix"])
+def test_matrix_engine_thin_inputs_bit_exact(cv, torch_dev, oracle_mod, shape, engine):
+    """Inputs of 1-3 rows: the column lines have fewer than 4 positions, so
+    their only k-group goes through the clamped loader (the planner's kin is
+    0); the automatic choice takes the matrix cores for these shapes too."""
+    N, M, P, Q = shape
+    assert cv.mfma_fits(N, M, P, Q)
+    A = synth.small_int(N, M, seed=7 * N + M)
+    _note("matrix engine thin input", shape, engine)
+    R = run(cv, torch_dev, A, P, Q, engine=engine)
+    ref = oracle_mod.forward(A, P, Q)
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)

@@ -436,7 +436,8 @@ def test_decomposition_reproduces_oracle(oracle_mod, shape):
 
 MFMA_SHAPES = [(1024, 1024, 32, 32), (256, 256, 16, 16), (512, 512, 16, 16), (40, 36, 16, 16),
                (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16), (34, 64, 16, 32), (300, 64, 28, 28),
-               (64, 64, 8, 8), (15, 7, 8, 4), (90, 70, 12, 12)]
+               (64, 64, 8, 8), (15, 7, 8, 4), (90, 70, 12, 12), (1, 9, 1, 4), (2, 7, 1, 4), (3, 7, 2, 4),
+               (3, 200, 2, 64)]
 
 
 def test_mfma_fits():
@@ -521,6 +522,74 @@ def test_mfma_plan_ownership(shape, n_cu):
         assert max(cost) <= 1.15 * (sum(cost) / 256) + 1   # balanced to a few percent
 
 
+def mfma_first_operand_rows_cols(job, info, N, M, P, Q, kin):
+    """Every A element the matrix-core kernel's first-operand loads touch for
+    one job, as (row, col) arrays: per visited (line, k-group), the 16*mt
+    lines of each tile row, clamped to the input, at the k-group's 4
+    positions, unclamped below kin and clamped to the line's end from kin on
+    (the kernel's two loaders)."""
+    o, kind, out, line0, line_end, b0, kg0, b1, kg1, nkg, plo, phi, k0 = [int(v) for v in job[1:14]]
+    nlines, npos = (M, N) if o else (N, M)
+    tm = info["nt"] if o else info["mt"]
+    d1lo = 0 if o else -(P - 1)
+    d1 = d1lo + np.arange(16 * tm)
+    rows, cols = [], []
+    for w, line, kg in mfma_visits(job):
+        q = np.clip(line + d1, 0, nlines - 1)
+        pos = k0 + 4 * kg + np.arange(4)
+        if kg >= kin:
+            pos = np.minimum(pos, npos - 1)
+        qq, pp = np.meshgrid(q, pos, indexing="ij")
+        rows.append(qq.ravel())
+        cols.append(pp.ravel())
+    if not rows:
+        return np.zeros(0, int), np.zeros(0, int)
+    lines, poss = np.concatenate(rows), np.concatenate(cols)
+    return (poss, lines) if o else (lines, poss)
+
+
+def c_trunc_div(a, b):
+    return int(a / b)   # C's integer division truncates toward zero
+
+
+# N <= 3 with P in {1, 2}: orientation-1 lines (columns of A) have fewer than
+# 4 positions, so the one k-group of such a line must take the clamped loader
+MFMA_THIN = [(N, 2 * Q - 1 + extra, P, Q) for N in (1, 2, 3) for P in (1, 2) for Q in (4, 5, 9, 16, 17, 33, 64)
+             for extra in (0, 7) if N >= 2 * P - 1]
+
+
+@pytest.mark.parametrize("shape", MFMA_THIN + [(64, 64, 8, 8), (5, 9, 3, 4), (1024, 1024, 32, 32),
+                                               (7, 200, 4, 64), (4, 7, 2, 4)])
+def test_mfma_first_operand_loads_stay_in_bounds(shape):
+    N, M, P, Q = shape
+    for n_cu in (256, 3):
+        info, jobs, _ = cv.mfma_plan(N, M, P, Q, n_cu)
+        for j in jobs:
+            o, nkg, k0, kin = int(j[1]), int(j[10]), int(j[13]), int(j[14])
+            npos = N if o else M
+            # kin counts exactly the k-groups whose 4 positions lie inside the line
+            assert kin == sum(1 for kg in range(nkg) if k0 + 4 * kg + 3 < npos)
+            assert nkg - kin <= (1 if o else 0)
+            r, c = mfma_first_operand_rows_cols(j, info, N, M, P, Q, kin)
+            assert r.size == 0 or (r.min() >= 0 and r.max() < N and c.min() >= 0 and c.max() < M), (shape, j)
+
+
+@pytest.mark.parametrize("shape", [(1, 9, 1, 4), (2, 7, 1, 4), (3, 7, 2, 4), (3, 200, 2, 64)])
+def test_mfma_bounds_check_catches_truncating_kin(shape):
+    """The count kin = (npos - 4 - k0) / 4 + 1 with C's truncating division is
+    1, not 0, for a line of 1-3 positions; the bounds model must flag it."""
+    N, M, P, Q = shape
+    assert cv.mfma_fits(N, M, P, Q) and cv.mfma_preferred(N, M, P, Q)
+    info, jobs, _ = cv.mfma_plan(N, M, P, Q, 256)
+    bad = 0
+    for j in jobs:
+        o, k0 = int(j[1]), int(j[13])
+        npos = N if o else M
+        r, c = mfma_first_operand_rows_cols(j, info, N, M, P, Q, c_trunc_div(npos - 4 - k0, 4) + 1)
+        bad += int(r.size > 0 and (r.max() >= N or c.max() >= M))
+    assert bad > 0
+
+
 def mfma_model_sums(A, P, Q, info, jobs):
     """What the matrix-core kernel computes, in NumPy: per job, the products of
     a block of lines (rows of A, or of A^T) with the Toeplitz band of the line,
@@ -588,7 +657,7 @@ def mfma_model_sums(A, P, Q, info, jobs):
 
 
 @pytest.mark.parametrize("shape", [(40, 36, 16, 16), (31, 31, 16, 16), (50, 47, 24, 24), (70, 40, 32, 16),
-                                   (34, 64, 16, 32)])
+                                   (34, 64, 16, 32), (1, 9, 1, 4), (2, 7, 1, 4), (3, 7, 2, 4), (3, 200, 2, 64)])
 @pytest.mark.parametrize("n_cu", [256, 5])
 def test_mfma_model_reproduces_oracle(oracle_mod, shape, n_cu):
     N, M, P, Q = shape
