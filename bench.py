@@ -21,11 +21,17 @@ FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain copy of
 known size (``--copy-calibration``); it is null unless the recorded summary was
 taken on the current kernel sources.
 
+Timing: `value` and `ms_per_step` come from the wall clock around exactly
+--steps steps between two device synchronisations; "step_ms_distribution"
+gives the median and 10th/90th percentiles of at least 50 single steps timed
+with HIP events on the launch stream.
+
 The CPU leg (skipped with --no-cpu) is the only part that runs the oracle: it
-times it on a bounded sample of entries ("cpu_baseline") and compares the same
-oracle entries with every form's GPU result ("accuracy": relative error over
-the sampled entries, and the largest error in units of the noise power, since
-the 1e6-magnitude exponential dominates every norm of R).
+compares the oracle's whole R with every form's whole R ("accuracy": relative
+Frobenius error, and the error in units of the noise power, since the
+1e6-magnitude exponential dominates every norm of R), then times the oracle's
+direct loops on a bounded sample of entries on all usable threads and on one
+("cpu_baseline", with the host's CPU model and core count).
 """
 from __future__ import annotations
 
@@ -126,43 +132,80 @@ def copy_calibration():
           flush=True)
 
 
-def cpu_leg(A, eta, seconds, k1s, k2s, gpu_values, noise_power):
-    """The oracle, as it stands: its entries at the sampled positions (k1s, k2s)
-    against every form's GPU values there, then its speed on a bounded sample
-    of R's upper entries."""
+def host_description():
+    """CPU model (from /proc/cpuinfo) and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+def cpu_leg(A, eta, seconds, gpu_results, noise_power):
+    """The oracle, as it stands.
+    accuracy: the oracle's whole R (its explicit-X route, eq. 2.2 as
+    X X^H / K, kept in the system temp folder between runs) against every
+    form's whole R: relative Frobenius error, and the error of the noise part
+    (the 1e6-magnitude exponential dominates every norm of R).
+    baseline: the oracle's direct loops timed on a bounded sample of R's upper
+    entries, on all usable threads and on one thread."""
     import numpy as np
     from oracle import oracle
 
-    threads = oracle.max_threads()
-    ref = oracle.entries(A, P, Q, k1s, k2s, threads=threads)
+    t0 = time.perf_counter()
+    Rref = oracle.forward_blas_cached(A, P, Q)
+    t_ref = time.perf_counter() - t0
+    noise_fro = noise_power * np.sqrt(P * Q)     # ||sigma^2 I||_F, the noise part's size
     accuracy = {}
-    for form, got in gpu_values.items():
-        d = np.asarray(got, dtype=np.complex128) - ref
-        accuracy[form] = {"rel_err_sampled": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+    nrm = np.linalg.norm(Rref)
+    for form, got in gpu_results.items():
+        d = np.asarray(got, dtype=np.complex128) - Rref
+        accuracy[form] = {"rel_err_full": float(np.linalg.norm(d) / nrm),
+                          "noise_rel_err_full": float(np.linalg.norm(d) / noise_fro),
                           "max_err_over_noise_power": float(np.abs(d).max() / noise_power)}
+    print(f"[bench] accuracy: oracle R in {t_ref:.1f} s", file=sys.stderr, flush=True)
+
     rng = np.random.default_rng(123)
     PQ = P * Q
 
     def sample(n):
         k1 = rng.integers(0, PQ, n)
         k2 = rng.integers(0, PQ, n)
-        lo, hi = np.minimum(k1, k2), np.maximum(k1, k2)
-        return lo, hi
+        return np.minimum(k1, k2), np.maximum(k1, k2)
 
-    n = 4 * threads
-    t0 = time.perf_counter()
-    oracle.entries(A, P, Q, *sample(n), threads=threads)
-    dt = time.perf_counter() - t0
-    n_big = max(n, int(n * (seconds / max(dt, 1e-3))))
-    k1, k2 = sample(n_big)
-    t0 = time.perf_counter()
-    oracle.entries(A, P, Q, k1, k2, threads=threads)
-    dt = time.perf_counter() - t0
-    per_matrix = dt * eta / n_big
-    baseline = {"value": 1.0 / per_matrix, "unit": "matrices/s", "cores": threads, "kind": "oracle",
-                "sample": f"{n_big} random upper-triangle entries of R for the same 1024x1024 input "
+    def timed(threads, budget):
+        n = 2 * threads
+        t0 = time.perf_counter()
+        oracle.entries(A, P, Q, *sample(n), threads=threads)
+        dt = time.perf_counter() - t0
+        n_big = max(n, int(n * (budget / max(dt, 1e-3))))
+        k1, k2 = sample(n_big)
+        t0 = time.perf_counter()
+        oracle.entries(A, P, Q, k1, k2, threads=threads)
+        dt = time.perf_counter() - t0
+        return n_big, dt, 1.0 / (dt * eta / n_big)
+
+    threads = oracle.max_threads()
+    n_all, dt_all, v_all = timed(threads, 0.65 * seconds)
+    n_one, dt_one, v_one = timed(1, 0.35 * seconds)
+    host = host_description()
+    baseline = {"value": v_all, "unit": "matrices/s", "cores": threads, "kind": "oracle",
+                "sample": f"{n_all} random upper-triangle entries of R for the same 1024x1024 input "
                           f"and 32x32 window (of {eta}), each a direct FP64 sum over all 986049 "
-                          f"positions, {dt:.1f} s on {threads} threads; scaled by {eta}/{n_big}"}
+                          f"positions, {dt_all:.1f} s on {threads} threads; scaled by {eta}/{n_all}",
+                "single_thread": {"value": v_one, "unit": "matrices/s", "cores": 1,
+                                  "sample": f"{n_one} entries, {dt_one:.1f} s on 1 thread; "
+                                            f"scaled by {eta}/{n_one}"},
+                "host": host}
     return baseline, accuracy
 
 
@@ -371,6 +414,19 @@ def main():
     value = args.steps / elapsed
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
 
+    # Distribution of single steps: HIP events on the stream the library
+    # launches on (torch's current stream), at least 50 steps.
+    n_dist = max(50, args.steps)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_dist)]
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    per_step = np.sort([a.elapsed_time(b) for a, b in evs])
+    step_dist = {"steps": n_dist, "median_ms": float(np.median(per_step)),
+                 "p10_ms": float(np.percentile(per_step, 10)), "p90_ms": float(np.percentile(per_step, 90))}
+
     # Per-kernel durations from HIP events on the launch stream, same workload.
     covest.timing_reset()
     covest.timing_enable(True)
@@ -418,12 +474,8 @@ def main():
         print(f"[bench] vector engine: {vms:.4f} ms/step", file=sys.stderr, flush=True)
         del wsv, Rv
 
-    # Sampled entries of every form's result, for the CPU leg's comparison
-    # with the oracle: every 8th diagonal entry and 64 random entries.
-    rng = np.random.default_rng(7)
-    sample_k1 = np.concatenate([np.arange(0, P * Q, 8), rng.integers(0, P * Q, 64)])
-    sample_k2 = np.concatenate([np.arange(0, P * Q, 8), rng.integers(0, P * Q, 64)])
-    gpu_values = {"recurrence_fp64": R.cpu().numpy()[sample_k1, sample_k2]}
+    # Every form's whole R, for the CPU leg's comparison with the oracle.
+    gpu_results = {"recurrence_fp64": R.cpu().numpy()}
     plain = {}
     if not args.no_plain:
         for prec, passes, peak_key in PLAIN_FORMS:
@@ -448,7 +500,7 @@ def main():
             covest.timing_enable(False)
             kms = rk["hankel_main"][1] / rk["hankel_main"][0]
             f_mfma = passes * 8.0 * cnt["K"] * cnt["eta"]
-            gpu_values["plain_" + prec] = Rp.cpu().numpy()[sample_k1, sample_k2]
+            gpu_results["plain_" + prec] = Rp.cpu().numpy()
             plain[prec] = {"ms_per_matrix": ms, "matrices_per_s": 1e3 / ms,
                            "hankel_main_ms": kms,
                            "mfma_tflops": f_mfma / (kms * 1e-3) / 1e12,
@@ -479,6 +531,7 @@ def main():
                                "32x32 window, R 1024x1024 complex128 over 993^2 positions",
                    "form": "recurrence", "engine": engine, "precision": "fp64",
                    "N": N, "M": M, "P": P, "Q": Q},
+        "step_ms_distribution": step_dist,
         "gflops_effective": f_nom / (ms_per_step * 1e-3) / 1e9,
         "gflops_algorithmic": f_alg / (ms_per_step * 1e-3) / 1e9,
         "kernels_ms": {main_name: main_avg_ms, "rec_finalize": fin_avg_ms},
@@ -496,12 +549,12 @@ def main():
     if not args.no_cpu:
         # noise power E|n|^2 of the input's noise part (the same draw without the exponential)
         noise_power = float(np.mean(np.abs(synth.wide_range(N, M, seed=3, amp=0.0)) ** 2))
-        baseline, accuracy = cpu_leg(A_np, cnt["eta"], args.cpu_seconds, sample_k1, sample_k2,
-                                     gpu_values, noise_power)
+        baseline, accuracy = cpu_leg(A_np, cnt["eta"], args.cpu_seconds, gpu_results, noise_power)
         out["cpu_baseline"] = baseline
-        out["accuracy"] = {"sample": f"{len(sample_k1)} entries of R (every 8th diagonal entry and "
-                                     f"64 random ones) against the oracle's direct FP64 sums; "
-                                     f"noise power {noise_power:.3f}", **accuracy}
+        out["accuracy"] = {"sample": f"the whole 1024x1024 R of every form against the oracle's R "
+                                     f"(explicit-X route, FP64); noise power {noise_power:.3f}; "
+                                     f"noise_rel_err_full = ||R - R_oracle||_F / (noise power * 32)",
+                           **accuracy}
     else:
         out["accuracy"] = None
     print(json.dumps(out), flush=True)

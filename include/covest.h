@@ -27,6 +27,14 @@
  *   - Every call returns a covest_status; no C++ exception crosses the ABI.
  *     On a non-OK status covest_last_error() describes the problem.
  *   - Calls on different streams may run concurrently.
+ *   - Non-finite input (NaN or Inf in A) is propagated, never checked.  By the
+ *     definition exactly the entries whose windows meet such an element are
+ *     non-finite.  The recurrence form recovers entries by adding and
+ *     subtracting edge sums of one combination (Sec. 3.3), so it may make
+ *     further entries of the same combination NaN as well; every entry it
+ *     returns finite is the definition's value.  For the plain (Hankel) form
+ *     only the propagation is stated: which entries turn non-finite depends
+ *     on its tiling.
  */
 #ifndef COVEST_H
 #define COVEST_H
@@ -39,7 +47,7 @@
 extern "C" {
 #endif
 
-#define COVEST_VERSION 2
+#define COVEST_VERSION 3
 
 typedef enum {
     COVEST_OK = 0,
@@ -141,17 +149,35 @@ int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t 
                       hipStream_t stream);
 
 /* Adjoint of the forward map for a real loss L (PyTorch's convention for
- * complex tensors: a gradient is dL/dRe + i dL/dIm).  dR (PQ x PQ complex64,
- * full matrix) is the gradient of L with respect to every entry of R; with
- * H = dR + dR^H, the result is dA = fold(H X) / K, where column (p, q) of X is
- * V^{p,q} and fold adds row i + P*j of the product onto A[p+i][q+j].  dA
- * (N x M complex64) is OVERWRITTEN.  normalize = 0 drops the 1/K.  Windows are
- * recomputed from A; nothing is stored by the forward call. */
+ * complex tensors: a gradient is dL/dRe + i dL/dIm; the adjoint is derived
+ * from eq. 2.2).  dR (PQ x PQ) is the gradient of L with respect to every
+ * entry of R; with H = dR + dR^H, the result is dA = fold(H X) / K, where
+ * column (p, q) of X is V^{p,q} and fold adds row i + P*j of the product onto
+ * A[p+i][q+j].  dA (N x M) is OVERWRITTEN.  Windows are recomputed from A;
+ * nothing is stored by the forward call.  A is complex64 as for the forward.
+ *   opts->prec    element type of dR and dA: complex128 for COVEST_PREC_FP64
+ *                 (also the default with opts = NULL), complex64 for every
+ *                 other precision -- the type of R the forward returns under
+ *                 the same options.  The arithmetic is FP64 either way.
+ *   opts->fill    FULL: H = dR + dR^H.  UPPER: the output's lower triangle is
+ *                 not a function of A, so only the entries k2 >= k1 of dR are
+ *                 read and H = triu(dR) + triu(dR)^H.
+ *   opts->normalize  0 drops the 1/K.  form, ring widths and engine are
+ *                 ignored.
+ * ws holds covest_backward_workspace_size() bytes (COVEST_ERR_WORKSPACE if
+ * smaller).  Errors: COVEST_ERR_INVALID_ARG for null pointers, dA overlapping A
+ * or dR, or (in _ex) lda < M, ldda < M, ldr < PQ; COVEST_ERR_SHAPE as for the
+ * forward; COVEST_ERR_UNSUPPORTED for P or Q above 64.
+ * covest_backward_ex takes strided views: A[n*lda + m], dR[k1*ldr + k2],
+ * dA[n*ldda + m] (elements). */
 int covest_backward_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,
                                    const covest_opts *opts, size_t *bytes);
 int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t M, int64_t P,
                     int64_t Q, const covest_opts *opts, void *ws, size_t ws_bytes,
                     hipStream_t stream);
+int covest_backward_ex(const void *A, int64_t lda, const void *dR, int64_t ldr, void *dA, int64_t ldda,
+                       int64_t N, int64_t M, int64_t P, int64_t Q, const covest_opts *opts, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
 
 /* Batched forward (Sec. 3.4, 5.1: many matrices at once keep every core busy).
  * covest_plan_batched_create copies the problem array, builds one work list for
@@ -213,7 +239,8 @@ int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *
 /* Minimum-variance (Capon) spectrum of a batch of estimated covariance
  * matrices (Sec. 2.3: R feeds the MVM / Capon estimator).  Each R is PQ x PQ
  * complex128, row-major, Hermitian positive definite (the FP64 output of
- * covest_forward or of a batched plan); matrix c starts at R + c*PQ*PQ.  On
+ * covest_forward or of a batched plan); matrix c starts at R + c*PQ*PQ.  Only
+ * the upper triangle (k2 >= k1) is read, so R from either fill works.  On
  * the grid w1 = -pi + 2 pi f1 / F1, w2 = -pi + 2 pi f2 / F2:
  *     S[c][f1][f2] = 1 / Re(a^H R^{-1} a),   a[i + P*j] = exp(i (w1 i + w2 j)),
  * S being count x F1 x F2 doubles (device).  Cholesky factor in FP64, R^{-1}

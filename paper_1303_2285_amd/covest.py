@@ -103,6 +103,8 @@ SIGNATURES = {
                                               ctypes.POINTER(ctypes.c_size_t)]),
     "covest_backward": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
                                _vp, ctypes.c_size_t, _vp]),
+    "covest_backward_ex": (_int, [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64,
+                                  ctypes.POINTER(covest_opts), _vp, ctypes.c_size_t, _vp]),
     "covest_plan_batched_create": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_problem), _i64,
                                           ctypes.POINTER(covest_opts), _vp]),
     "covest_plan_batched_create_ex": (_int, [ctypes.POINTER(_vp), ctypes.POINTER(covest_problem_ex), _i64,
@@ -261,22 +263,41 @@ def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="fu
     return R
 
 
-def covest_backward(A, dR, P: int, Q: int, *, normalize=True, workspace=None):
-    """dA = fold((dR + dR^H) X) / K for the complex64 gradient dR (PQ x PQ)."""
+def covest_backward(A, dR, P: int, Q: int, *, normalize=True, fill="full", precision=None, out=None,
+                    workspace=None):
+    """dA = fold(H X) / K with H = dR + dR^H (fill "full") or triu(dR) + triu(dR)^H
+    (fill "upper": the gradient of an upper-only R).
+
+    precision "fp64" takes a complex128 dR and returns complex128 dA; "fp32"
+    takes and returns complex64; None follows dR's dtype.  A and dR may be
+    strided views with unit column stride; `out` (N x M, the same dtype,
+    unit column stride) receives dA if given.
+    """
     torch = _torch()
     _check_input(A)
     N, M = A.shape
-    o = make_opts("auto", "fp32", "full", normalize)
-    dR = dR.to(torch.complex64).contiguous()
+    if precision is None:
+        precision = "fp64" if dR.dtype == torch.complex128 else "fp32"
+    if precision not in ("fp64", "fp32"):
+        raise ValueError("the adjoint's precision is fp64 or fp32")
+    gdtype = torch.complex128 if precision == "fp64" else torch.complex64
+    o = make_opts("auto", precision, fill, normalize)
+    if dR.dtype != gdtype or dR.stride(-1) != 1:
+        dR = dR.to(gdtype).contiguous()
     if dR.shape != (P * Q, P * Q):
         raise ValueError("dR must be PQ x PQ")
-    dA = torch.empty_like(A)
-    need = backward_workspace_size(N, M, P, Q, precision="fp32", normalize=normalize)
+    if out is None:
+        dA = torch.empty((N, M), dtype=gdtype, device=A.device)
+    else:
+        dA = out
+        if dA.dtype != gdtype or dA.shape != (N, M) or dA.stride(1) != 1:
+            raise ValueError("out has the wrong dtype, shape or layout")
+    need = backward_workspace_size(N, M, P, Q, precision=precision, normalize=normalize)
     ws, nbytes = _workspace(need, A.device) if workspace is None else (workspace, workspace.numel())
-    _check(lib().covest_backward(
-        ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(dR.data_ptr()), ctypes.c_void_p(dA.data_ptr()),
-        N, M, P, Q, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
-        nbytes, _stream_handle(A.device)))
+    _check(lib().covest_backward_ex(
+        ctypes.c_void_p(A.data_ptr()), A.stride(0), ctypes.c_void_p(dR.data_ptr()), dR.stride(0),
+        ctypes.c_void_p(dA.data_ptr()), dA.stride(0), N, M, P, Q, ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), nbytes, _stream_handle(A.device)))
     return dA
 
 
@@ -414,7 +435,7 @@ def _make_autograd():
         def backward(ctx, gR):
             (A,) = ctx.saved_tensors
             dA = covest_backward(A.detach(), gR.to(torch.complex64).contiguous(), ctx.P, ctx.Q,
-                                 normalize=ctx.normalize)
+                                 normalize=ctx.normalize, precision="fp32")
             return dA, None, None, None, None
 
     return CovEst

@@ -1088,8 +1088,9 @@ int covest_backward_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,
     return ok();
 }
 
-int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t M, int64_t P, int64_t Q,
-                    const covest_opts *opts, void *ws, size_t ws_bytes, hipStream_t stream)
+int covest_backward_ex(const void *A, int64_t lda, const void *dR, int64_t ldr, void *dA, int64_t ldda,
+                       int64_t N, int64_t M, int64_t P, int64_t Q, const covest_opts *opts, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
 {
     const covest_opts o = resolve_opts(opts);
     int st = check_opts(o);
@@ -1097,7 +1098,23 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
     st = check_shape(N, M, P, Q);
     if (st != COVEST_OK) return st;
     if (!A || !dR || !dA) return fail(COVEST_ERR_INVALID_ARG, "A, dR and dA must be non-null device pointers");
-    if (dA == A || dA == dR) return fail(COVEST_ERR_INVALID_ARG, "dA must not alias A or dR");
+    if (lda < M || ldda < M)
+        return fail(COVEST_ERR_INVALID_ARG, "lda (%lld) and ldda (%lld) must be >= M (%lld)", (long long)lda,
+                    (long long)ldda, (long long)M);
+    if (ldr < P * Q)
+        return fail(COVEST_ERR_INVALID_ARG, "ldr (%lld) < PQ (%lld)", (long long)ldr, (long long)(P * Q));
+    // element types: those of R under the same options (complex128 for FP64)
+    const bool fp64 = o.prec == COVEST_PREC_FP64;
+    const size_t ge = fp64 ? 16 : 8;
+    auto span = [](const void *p, int64_t rows, int64_t ld, int64_t cols, size_t es) {
+        const char *b = static_cast<const char *>(p);
+        return std::make_pair(b, b + ((rows - 1) * ld + cols) * (int64_t)es);
+    };
+    auto overlap = [](std::pair<const char *, const char *> x, std::pair<const char *, const char *> y) {
+        return x.first < y.second && y.first < x.second;
+    };
+    const auto sA = span(A, N, lda, M, 8), sG = span(dR, P * Q, ldr, P * Q, ge), sD = span(dA, N, ldda, M, ge);
+    if (overlap(sD, sA) || overlap(sD, sG)) return fail(COVEST_ERR_INVALID_ARG, "dA must not overlap A or dR");
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the adjoint supports P, Q <= %d", kMaxWindow);
     const AdjGeom g = adj_geometry((int)N, (int)M, (int)P, (int)Q);
@@ -1108,11 +1125,13 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
                     (long long)g.frame_jobs);
     AdjArgs aa{};
     aa.A = static_cast<const float2 *>(A);
-    aa.lda = M;
-    aa.G = static_cast<const float2 *>(dR);
-    aa.ldg = P * Q;
-    aa.dA = static_cast<float2 *>(dA);
-    aa.ldda = M;
+    aa.lda = lda;
+    aa.G = dR;
+    aa.ldg = ldr;
+    aa.dA = dA;
+    aa.ldda = ldda;
+    aa.g_fp64 = fp64 ? 1 : 0;
+    aa.upper = o.fill == COVEST_FILL_UPPER ? 1 : 0;
     aa.N = (int)N;
     aa.M = (int)M;
     aa.P = (int)P;
@@ -1131,6 +1150,12 @@ int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t 
         return launch_adjoint(aa, g.n_lags, g.lds_tables, g.interior_blocks, g.lds_interior, g.frame_jobs, stream);
     }));
     return finish_call(stream);
+}
+
+int covest_backward(const void *A, const void *dR, void *dA, int64_t N, int64_t M, int64_t P, int64_t Q,
+                    const covest_opts *opts, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return covest_backward_ex(A, M, dR, P * Q, dA, M, N, M, P, Q, opts, ws, ws_bytes, stream);
 }
 
 int covest_plan_batched_create(covest_plan **out, const covest_problem *problems, int64_t count,

@@ -15,10 +15,12 @@ constexpr int kAdjFrameLds = 64 * 1024;   // LDS of a frame job: weight and A sl
 struct AdjArgs {
     const float2 *A;
     int64_t lda;
-    const float2 *G;            // dL/dR, PQ x PQ complex64
+    const void *G;              // dL/dR, PQ x PQ: complex128 (g_fp64) or complex64
     int64_t ldg;
-    float2 *dA;
+    void *dA;                   // N x M: complex128 (g_fp64) or complex64
     int64_t ldda;
+    int g_fp64;                 // 1: G and dA are complex128
+    int upper;                  // 1: only G's entries with k2 >= k1 count (H = triu(G) + triu(G)^H)
     int N, M, P, Q, Kr, Kc;
     int ir0, ir1, ic0, ic1;     // interior outputs [ir0, ir1) x [ic0, ic1)
     int ndc;                    // 2Q-1 rounded up to a multiple of 16

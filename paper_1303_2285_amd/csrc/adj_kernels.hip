@@ -38,12 +38,27 @@ __device__ __forceinline__ void cmla(double2 &acc, const double2 a, const double
     acc.y = fma(a.y, w.x, acc.y);
 }
 
-// H[a][b] = G[a][b] + conj(G[b][a]) from the complex64 gradient
+__device__ __forceinline__ double2 g_entry(const AdjArgs &aa, int a, int b)
+{
+    const int64_t e = (int64_t)a * aa.ldg + b;
+    if (aa.g_fp64) return static_cast<const double2 *>(aa.G)[e];
+    const float2 g = static_cast<const float2 *>(aa.G)[e];
+    return make_double2((double)g.x, (double)g.y);
+}
+
+// H[a][b] = G[a][b] + conj(G[b][a]); for an upper-only output the lower
+// triangle of R is not a function of A, so only G's entries with column >= row
+// count (G[a][b] for b >= a, G[b][a] for a >= b; both on the diagonal)
 __device__ __forceinline__ double2 h_entry(const AdjArgs &aa, int a, int b)
 {
-    const float2 g1 = aa.G[(int64_t)a * aa.ldg + b];
-    const float2 g2 = aa.G[(int64_t)b * aa.ldg + a];
-    return make_double2((double)g1.x + (double)g2.x, (double)g1.y - (double)g2.y);
+    double2 h = dz();
+    if (!aa.upper || b >= a) h = g_entry(aa, a, b);
+    if (!aa.upper || a >= b) {
+        const double2 g2 = g_entry(aa, b, a);
+        h.x += g2.x;
+        h.y -= g2.y;
+    }
+    return h;
 }
 
 // D1: per lag, the prefix-sum table S[i][j] = sum_{i' < i, j' < j} T[i'][j'],
@@ -107,7 +122,9 @@ __device__ __forceinline__ void store_da(const AdjArgs &aa, int r, int c, double
         s.x = s.x / K;
         s.y = s.y / K;
     }
-    aa.dA[(int64_t)r * aa.ldda + c] = make_float2((float)s.x, (float)s.y);
+    const int64_t e = (int64_t)r * aa.ldda + c;
+    if (aa.g_fp64) static_cast<double2 *>(aa.dA)[e] = s;
+    else static_cast<float2 *>(aa.dA)[e] = make_float2((float)s.x, (float)s.y);
 }
 
 // h_(dr,dc)(r, c) from the lag's prefix table; false (and zero) when no

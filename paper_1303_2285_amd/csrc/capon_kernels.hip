@@ -12,7 +12,8 @@
 //
 // One workgroup per matrix (n = PQ <= 256); for n <= 128 everything but the
 // DFT lives in LDS, above that the packed factor lives in the workspace:
-//   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2);
+//   1. the lower triangle of R into LDS (packed, row i at i(i+1)/2), read as
+//      the conjugate of the upper triangle (the part every fill writes);
 //   2. Cholesky R = L L^H in place (right-looking, FP64, one barrier per
 //      column: the column's scaling is deferred to one pass at the end);
 //   3. W = L^{-1} in place, columns from n-1 down to 0, two per step: with
@@ -61,10 +62,15 @@ __global__ void __launch_bounds__(kCT) capon_kernel(CaponArgs ca)
     double2 *Lp = GF ? ca.F + mat * (size_t)tri(n) : sh;
     double2 *const colbuf = GF ? sh : sh + tri(n);   // n entries, then the lag sums
 
-    // 1. lower triangle of R
+    // 1. lower triangle of R, taken from the upper one (R[i][k] = conj(R[k][i])):
+    // both output fills of the forward write the upper triangle, so R from a
+    // FILL_UPPER call works too.  Reads follow R's memory order.
     for (int e = tid; e < n * n; e += kCT) {
-        const int i = e / n, k = e - i * n;
-        if (k <= i) Lp[tri(i) + k] = R[e];
+        const int k = e / n, i = e - k * n;
+        if (k <= i) {
+            const double2 v = R[e];
+            Lp[tri(i) + k] = make_double2(v.x, -v.y);
+        }
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert cv.version() == 2
+    assert cv.version() == 3
 
 
 def _opts(**kw):
@@ -170,3 +170,46 @@ def test_binding_short_names():
     assert cv.CovEst is cv.CovEst
     with pytest.raises(AttributeError):
         cv.no_such_name
+
+
+def test_backward_argument_errors_before_device_use():
+    """covest_backward_ex checks pointers, strides, overlap, shape and the
+    workspace before any device call; opts->prec picks the element types
+    (complex128 for FP64, the NULL-opts default), so the overlap check uses
+    16-byte elements there."""
+    L = cv.lib()
+    A, G, D = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 40)
+    n = ctypes.c_size_t(0)
+    assert L.covest_backward_workspace_size(64, 64, 8, 8, None, ctypes.byref(n)) == cv.OK
+    ws, need = ctypes.c_void_p(1 << 44), n.value
+    for prec in ("fp64", "fp32"):
+        for fill in ("full", "upper"):
+            o = _opts(precision=prec, fill=fill)
+            # strides
+            assert L.covest_backward_ex(A, 63, G, 64, D, 64, 64, 64, 8, 8, o, ws, need, None) == cv.ERR_INVALID_ARG
+            assert L.covest_backward_ex(A, 64, G, 63, D, 64, 64, 64, 8, 8, o, ws, need, None) == cv.ERR_INVALID_ARG
+            assert "ldr" in L.covest_last_error().decode()
+            assert L.covest_backward_ex(A, 64, G, 64, D, 63, 64, 64, 8, 8, o, ws, need, None) == cv.ERR_INVALID_ARG
+            # null pointers, shapes, P above the limit
+            assert L.covest_backward(None, G, D, 64, 64, 8, 8, o, ws, need, None) == cv.ERR_INVALID_ARG
+            assert L.covest_backward(A, G, D, 64, 64, 65, 8, o, ws, need, None) == cv.ERR_SHAPE
+            assert L.covest_backward(A, G, D, 300, 300, 65, 8, o, ws, 1 << 40, None) == cv.ERR_UNSUPPORTED
+            # workspace
+            assert L.covest_backward(A, G, D, 64, 64, 8, 8, o, ws, need - 1, None) == cv.ERR_WORKSPACE
+            assert L.covest_backward(A, G, D, 64, 64, 8, 8, o, None, need, None) == cv.ERR_WORKSPACE
+    # dA overlapping A (strided: its last row reaches A) or dR, by element size
+    o64, o32 = _opts(precision="fp64"), _opts(precision="fp32")
+    base = 1 << 20
+    # A spans [base, base + 64*64*8); a complex128 dA of 64 x 64 starting 32 KiB
+    # before A ends overlaps it
+    assert L.covest_backward(ctypes.c_void_p(base), G, ctypes.c_void_p(base + 64 * 64 * 8 - 32768), 64, 64, 8, 8,
+                             o64, ws, need, None) == cv.ERR_INVALID_ARG
+    assert "overlap" in L.covest_last_error().decode()
+    # dR is 64 x 64 complex128 = 64 KiB: a dA right after a complex64-sized dR
+    # overlaps only under FP64
+    dr_c64 = 64 * 64 * 8
+    assert L.covest_backward(A, ctypes.c_void_p(base << 4), ctypes.c_void_p((base << 4) + dr_c64), 64, 64, 8, 8,
+                             o64, ws, need, None) == cv.ERR_INVALID_ARG
+    assert L.covest_backward(A, ctypes.c_void_p(base << 4), ctypes.c_void_p((base << 4) + dr_c64), 64, 64, 8, 8,
+                             o32, None, need, None) == cv.ERR_WORKSPACE   # passes the overlap check
+    assert L.covest_backward(A, G, A, 64, 64, 8, 8, None, ws, need, None) == cv.ERR_INVALID_ARG

@@ -193,3 +193,78 @@ def test_backward_errors(cv, tdev):
     with pytest.raises(cv.CovestError) as e:
         cv.covest_backward(A, torch.zeros((81, 81), dtype=torch.complex64, device=dev), 9, 9)
     assert e.value.status == cv.ERR_SHAPE
+
+
+def _rand_g(rng, n, dtype):
+    return (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(dtype)
+
+
+@pytest.mark.parametrize("shape", SMALL + [(100, 90, 32, 32), (300, 40, 20, 3)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_fp64_vs_oracle(cv, tdev, oracle_mod, shape):
+    """The FP64 option: complex128 dR in, complex128 dA out, FP64 throughout;
+    against the oracle's adjoint (direct loops, or the BLAS route for the
+    wider windows) to 1e-12."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    rng = np.random.default_rng(N * 7 + M)
+    A = synth.gaussian(N, M, seed=N + 5 * M)
+    G = _rand_g(rng, P * Q, np.complex128)
+    _note("adjoint fp64", shape)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q)
+    torch.cuda.synchronize()
+    assert dA.dtype == torch.complex128
+    ref = oracle_mod.adjoint(A, G, P, Q) if P * Q <= 256 else oracle_mod.adjoint_blas(A, G, P, Q)
+    assert rel(dA.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("shape", [(20, 18, 4, 4), (64, 64, 8, 8), (70, 50, 16, 12)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_upper_fill(cv, tdev, oracle_mod, shape, precision, tol):
+    """fill='upper': the gradient of an upper-only output is the adjoint of
+    triu(dR); the lower triangle of dR is never read (NaN there must not
+    reach dA)."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    rng = np.random.default_rng(N + 11 * M)
+    A = synth.gaussian(N, M, seed=3 * N + M)
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    G = _rand_g(rng, P * Q, dt)
+    Gu = np.triu(G)
+    Gnan = G.copy()
+    Gnan[np.tril_indices(P * Q, -1)] = np.nan
+    _note("adjoint upper fill", shape, precision)
+    At = torch.from_numpy(A).to(dev)
+    dA = cv.covest_backward(At, torch.from_numpy(Gnan).to(dev), P, Q, fill="upper", precision=precision)
+    torch.cuda.synchronize()
+    got = dA.cpu().numpy().astype(np.complex128)
+    assert np.all(np.isfinite(got))
+    assert rel(got, oracle_mod.adjoint(A, Gu, P, Q)) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_adjoint_strided_views(cv, tdev, oracle_mod, precision, tol):
+    """A, dR and dA as views into larger arrays (row strides above their
+    widths): covest_backward_ex writes only the view."""
+    torch, dev = tdev
+    N, M, P, Q = 60, 70, 8, 6
+    rng = np.random.default_rng(5)
+    A = synth.gaussian(N, M, seed=8)
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    tdt = torch.complex128 if precision == "fp64" else torch.complex64
+    G = _rand_g(rng, P * Q, dt)
+    bigA = torch.zeros((N + 3, M + 29), dtype=torch.complex64, device=dev)
+    bigA[2:2 + N, 5:5 + M] = torch.from_numpy(A).to(dev)
+    bigG = torch.zeros((P * Q + 4, P * Q + 13), dtype=tdt, device=dev)
+    bigG[1:1 + P * Q, 3:3 + P * Q] = torch.from_numpy(G).to(dev)
+    out = torch.full((N + 2, M + 9), 7.0 + 7.0j, dtype=tdt, device=dev)
+    _note("adjoint strided views", precision)
+    cv.covest_backward(bigA[2:2 + N, 5:5 + M], bigG[1:1 + P * Q, 3:3 + P * Q], P, Q, precision=precision,
+                       out=out[1:1 + N, 4:4 + M])
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert rel(o[1:1 + N, 4:4 + M].astype(np.complex128), oracle_mod.adjoint(A, G, P, Q)) <= tol
+    mask = np.ones(o.shape, bool)
+    mask[1:1 + N, 4:4 + M] = False
+    assert np.all(o[mask] == 7.0 + 7.0j)

@@ -187,3 +187,23 @@ def test_gpu_three_exponentials_16x16(cv, tdev):
     S = cv.covest_capon_spectrum(R, P, Q, 128, 128).cpu().numpy()
     peak_checks(S, w, 128, 128)
 
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("P,Q", [(10, 10), (16, 16)])
+def test_gpu_upper_fill_input(cv, tdev, oracle_mod, P, Q):
+    """R from the forward with fill='upper' (the lower triangle left as the
+    caller's zeros) gives the same spectrum as the full R: the kernel reads
+    only the upper triangle."""
+    torch, dev = tdev
+    img = synth.exponentials(120, 110, 21, n_exp=2)
+    _note("capon of an upper-fill R", P, Q)
+    At = torch.from_numpy(img).to(dev)
+    Ru = cv.covest_forward(At, P, Q, fill="upper")
+    Rf = cv.covest_forward(At, P, Q, fill="full")
+    assert torch.count_nonzero(torch.tril(Ru, -1)).item() == 0
+    Su = cv.covest_capon_spectrum(Ru, P, Q, 48, 40).cpu().numpy()
+    Sf = cv.covest_capon_spectrum(Rf, P, Q, 48, 40).cpu().numpy()
+    assert np.array_equal(Su, Sf)
+    ref = oracle_mod.capon(oracle_mod.forward(img, P, Q, threads=oracle_mod.max_threads()), P, Q, 48, 40)
+    assert np.max(np.abs(Su - ref) / np.abs(ref)) <= 1e-9

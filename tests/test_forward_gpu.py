@@ -242,3 +242,30 @@ def test_workspace_too_small(cv, torch_dev):
     st = cv.lib().covest_forward(ctypes.c_void_p(At.data_ptr()), 64, 64, 8, 8, ctypes.c_void_p(R.data_ptr()),
                                  ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), 16, None)
     assert st == cv.ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+@pytest.mark.parametrize("engine", ["matrix", "vector"])
+@pytest.mark.parametrize("shape", [(64, 64, 8, 8), (90, 70, 12, 9)], ids=lambda s: "x".join(map(str, s)))
+def test_non_finite_input(cv, torch_dev, oracle_mod, shape, engine, bad):
+    """Non-finite elements at a corner, on an edge and in the interior of an
+    integer input.  The definition (eq. 2.2) makes exactly the entries whose
+    windows meet such an element non-finite; the recurrence forms sums by
+    adding and subtracting edge sums (Sec. 3.3), so it may also spread them to
+    other entries of the same combination.  What holds: every entry the
+    oracle makes non-finite is non-finite here too, and every finite entry
+    here equals the oracle's bit for bit."""
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N + M + (1 if bad == "inf" else 0)).astype(np.complex64)
+    v = np.complex64(complex(np.nan, 0.0) if bad == "nan" else complex(0.0, np.inf))
+    for (r, c) in [(0, 0), (0, M // 2), (N // 2 + 1, M // 2 - 1)]:
+        A[r, c] = v
+    _note("non-finite input", shape, engine, bad)
+    R = gpu_forward(cv, torch_dev, A, P, Q, engine=engine)
+    ref = oracle_mod.forward(A, P, Q)
+    bad_ref = ~np.isfinite(ref)
+    bad_gpu = ~np.isfinite(R)
+    assert bad_ref.any()
+    assert np.all(bad_gpu[bad_ref])
+    fin = ~bad_gpu
+    assert np.array_equal(R[fin], ref[fin])
