@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define COVEST_VERSION 3
+#define COVEST_VERSION 4
 
 typedef enum {
     COVEST_OK = 0,
@@ -147,6 +147,33 @@ int covest_forward(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, vo
 int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t P, int64_t Q,
                       void *R, int64_t ldr, const covest_opts *opts, void *ws, size_t ws_bytes,
                       hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * recurrence form of covest_forward_ex with no workspace argument and no
+ * device allocation at all.  The plan's job tables and the FP64 workspace live
+ * in one fixed device array of COVEST_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU,
+ * held from the library's first use of that GPU until the process ends; the
+ * call neither calls hipMalloc nor hipFree.  A, R, strides and options are as
+ * for covest_forward_ex; results are bitwise those of covest_forward_ex with
+ * the same options.
+ *   - form must be AUTO or RECURRENCE and prec FP64 or FP32 (the plain form:
+ *     COVEST_ERR_UNSUPPORTED).
+ *   - A shape whose tables plus workspace exceed the array is rejected with
+ *     COVEST_ERR_WORKSPACE before any device work (covest_workspace_size()
+ *     plus a few hundred KB of tables must fit; the 1024 x 1024 input with a
+ *     32 x 32 window needs about 15 MB).
+ *   - Every call on one GPU shares that GPU's array.  The host copies a
+ *     shape's tables into it (hipMemcpyAsync on `stream`, from the library's
+ *     cached host plan) when the previous call on that GPU used another
+ *     shape.  Calls that may overlap on one GPU -- on different streams
+ *     without ordering between them, or from several host threads -- race on
+ *     the array and give wrong results; order them on one stream.  Nothing in
+ *     the array needs to start at zero: every kernel writes each workspace
+ *     word before reading it. */
+#define COVEST_NOALLOC_SCRATCH_BYTES (32u << 20)
+int covest_forward_noalloc(const void *A, int64_t lda, int64_t N, int64_t M, int64_t P, int64_t Q,
+                           void *R, int64_t ldr, const covest_opts *opts, hipStream_t stream);
 
 /* Adjoint of the forward map for a real loss L (PyTorch's convention for
  * complex tensors: a gradient is dL/dRe + i dL/dIm; the adjoint is derived

@@ -99,6 +99,8 @@ SIGNATURES = {
                               ctypes.c_size_t, _vp]),
     "covest_forward_ex": (_int, [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64,
                                  ctypes.POINTER(covest_opts), _vp, ctypes.c_size_t, _vp]),
+    "covest_forward_noalloc": (_int, [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64,
+                                      ctypes.POINTER(covest_opts), _vp]),
     "covest_backward_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
                                               ctypes.POINTER(ctypes.c_size_t)]),
     "covest_backward": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(covest_opts),
@@ -261,6 +263,27 @@ def covest_forward(A, P: int, Q: int, *, form="auto", precision="fp64", fill="fu
         R.stride(0), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
         nbytes, _stream_handle(A.device)))
     return R
+
+
+def covest_forward_noalloc(A, P: int, Q: int, out, *, precision="fp64", fill="full", normalize=True,
+                           engine="auto"):
+    """covest_forward's recurrence into the caller's `out` (PQ x PQ, complex128
+    for "fp64", complex64 for "fp32", unit column stride) with no device
+    allocation: the library's fixed per-GPU scratch holds its tables and
+    workspace.  Calls on one GPU share that scratch, so they must not overlap."""
+    _check_input(A)
+    N, M = A.shape
+    o = make_opts("recurrence", precision, fill, normalize, 0, 0, engine)
+    torch = _torch()
+    rdtype = torch.complex128 if o.prec == 0 else torch.complex64
+    if out.dtype != rdtype or tuple(out.shape) != (P * Q, P * Q) or out.stride(1) != 1:
+        raise ValueError("out has the wrong dtype, shape or layout")
+    if out.device != A.device:
+        raise ValueError("out must be on A's device")
+    _check(lib().covest_forward_noalloc(
+        ctypes.c_void_p(A.data_ptr()), A.stride(0), N, M, P, Q, ctypes.c_void_p(out.data_ptr()),
+        out.stride(0), ctypes.byref(o), _stream_handle(A.device)))
+    return out
 
 
 def covest_backward(A, dR, P: int, Q: int, *, normalize=True, fill="full", precision=None, out=None,

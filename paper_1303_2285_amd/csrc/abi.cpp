@@ -24,6 +24,7 @@
 #include "adj_internal.hpp"
 #include "capon_internal.hpp"
 #include "launch.hpp"
+#include "noalloc_internal.hpp"
 #include "plan.hpp"
 
 using namespace covest;
@@ -277,46 +278,57 @@ int finish_call(hipStream_t stream)
     return ok();
 }
 
-int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
-                const covest_opts &o, void *ws, size_t ws_bytes, hipStream_t stream)
+// Engine of the main pass for one call: 1 vector, 2 matrix cores; a status
+// when the requested engine cannot run the shape.
+int rec_engine(int N, int M, int P, int Q, int64_t lda, const covest_opts &o, int *engine)
 {
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
     if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form computes in FP64 (prec FP64 or FP32 output)");
-    int engine = pick_engine(N, M, P, Q, o);
-    if (engine == 0)
+    int e = pick_engine(N, M, P, Q, o);
+    if (e == 0)
         return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N >= 2P-1, M >= 2Q-1 and a lag "
                                             "block of at most 8 tiles of 16 x 16 with little padding");
     // the matrix-core kernel addresses A with 32-bit element offsets
-    if (engine == 2 && (int64_t)N * lda + M >= ((int64_t)1 << 31)) {
+    if (e == 2 && (int64_t)N * lda + M >= ((int64_t)1 << 31)) {
         if (o.engine == COVEST_ENGINE_MATRIX)
             return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core engine needs N * lda < 2^31");
-        engine = 1;
+        e = 1;
     }
-    DevPlan *dp = nullptr;
-    int st = get_plan(N, M, P, Q, o.ring_cols, o.ring_rows, engine, &dp);
-    if (st != COVEST_OK) return st;
-    const ShapePlan &sp = dp->sp;
-    if (ws_bytes < sp.ws_bytes || (sp.ws_bytes > 0 && ws == nullptr))
-        return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", sp.ws_bytes, ws_bytes);
-    const Inst in = make_inst(sp, A, lda, R, ldr, ws, o);
+    *engine = e;
+    return COVEST_OK;
+}
+
+// Device copies of one shape plan's tables.
+struct DevTables {
+    const Job *jobs;
+    const LagGroup *groups;
+    const FinItem *items;
+    const MJob *mjobs;
+    int xcd_remap;
+};
+
+// The recurrence's launches for one problem: main pass (matrix cores or
+// vector units), then the finalize.
+int rec_launch(const ShapePlan &sp, const DevTables &t, const Inst &in, hipStream_t stream)
+{
     if (!sp.mjobs.empty()) {
         MfmaArgs ma{};
-        ma.jobs = dp->d_mjobs;
+        ma.jobs = t.mjobs;
         ma.n_jobs = (int)sp.mjobs.size();
-        ma.xcd_remap = dp->xcd_remap;
+        ma.xcd_remap = t.xcd_remap;
         ma.inst = in;
         HIP_TRY(timed("rec_mfma", stream, [&] {
             return launch_rec_mfma(ma, sp.mt, sp.nt, (int)sp.mjobs.size(), sp.lds_main, stream);
         }));
     } else if (!sp.jobs.empty()) {
         MainArgs ma{};
-        ma.jobs = dp->d_jobs;
-        ma.groups = dp->d_groups;
+        ma.jobs = t.jobs;
+        ma.groups = t.groups;
         ma.insts = nullptr;
         ma.n_jobs = (int)sp.jobs.size();
-        ma.xcd_remap = dp->xcd_remap;
+        ma.xcd_remap = t.xcd_remap;
         ma.use_inline = 1;
         ma.inst_inline = in;
         HIP_TRY(timed("rec_main", stream, [&] {
@@ -324,7 +336,7 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
         }));
     }
     FinArgs fa{};
-    fa.items = dp->d_items;
+    fa.items = t.items;
     fa.insts = nullptr;
     fa.n_items = (int)sp.items.size();
     fa.use_inline = 1;
@@ -333,6 +345,94 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
         return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, sp.fin_variant, stream);
     }));
     return finish_call(stream);
+}
+
+int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
+                const covest_opts &o, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    int engine = 0;
+    int st = rec_engine(N, M, P, Q, lda, o, &engine);
+    if (st != COVEST_OK) return st;
+    DevPlan *dp = nullptr;
+    st = get_plan(N, M, P, Q, o.ring_cols, o.ring_rows, engine, &dp);
+    if (st != COVEST_OK) return st;
+    const ShapePlan &sp = dp->sp;
+    if (ws_bytes < sp.ws_bytes || (sp.ws_bytes > 0 && ws == nullptr))
+        return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", sp.ws_bytes, ws_bytes);
+    const Inst in = make_inst(sp, A, lda, R, ldr, ws, o);
+    return rec_launch(sp, DevTables{dp->d_jobs, dp->d_groups, dp->d_items, dp->d_mjobs, dp->xcd_remap}, in,
+                      stream);
+}
+
+// ------------------------------------------------------ fixed scratch ----
+// covest_forward_noalloc: the same plan and kernels as rec_forward, with the
+// plan's tables and the workspace in the device's fixed scratch array instead
+// of cached device allocations and a caller workspace.  The tables are copied
+// into the scratch when the shape differs from the one whose tables it holds.
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct ScratchLayout {
+    size_t jobs, groups, items, mjobs, ws, total;
+};
+
+ScratchLayout scratch_layout(const ShapePlan &sp)
+{
+    ScratchLayout l{};
+    l.jobs = 0;
+    l.groups = l.jobs + align256(sizeof(Job) * sp.jobs.size());
+    l.items = l.groups + align256(sizeof(LagGroup) * sp.groups.size());
+    l.mjobs = l.items + align256(sizeof(FinItem) * sp.items.size());
+    l.ws = l.mjobs + align256(sizeof(MJob) * sp.mjobs.size());
+    l.total = l.ws + sp.ws_bytes;
+    return l;
+}
+
+std::mutex g_smu;
+std::map<int, PlanKey> g_scratch_tables;   // device -> plan whose tables its scratch holds
+
+template <class T>
+hipError_t copy_table(unsigned char *dst, const std::vector<T> &src, hipStream_t stream)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, stream);
+}
+
+int rec_forward_noalloc(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
+                        const covest_opts &o, hipStream_t stream)
+{
+    int engine = 0;
+    int st = rec_engine(N, M, P, Q, lda, o, &engine);
+    if (st != COVEST_OK) return st;
+    const auto sp = host_plan(N, M, P, Q, o.ring_cols, o.ring_rows, engine);
+    const ScratchLayout l = scratch_layout(*sp);
+    if (l.total > kNoallocScratchBytes)
+        return fail(COVEST_ERR_WORKSPACE, "this shape needs %zu bytes of scratch; the fixed scratch holds %zu",
+                    l.total, (size_t)kNoallocScratchBytes);
+    void *base_v = nullptr;
+    HIP_TRY(noalloc_scratch(&base_v));
+    unsigned char *base = static_cast<unsigned char *>(base_v);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int cus = cus_of_device(dev);
+    const PlanKey key = std::make_tuple(cus, N, M, P, Q, o.ring_cols, o.ring_rows, engine);
+    {
+        std::lock_guard<std::mutex> lk(g_smu);
+        auto it = g_scratch_tables.find(dev);
+        if (it == g_scratch_tables.end() || it->second != key) {
+            if (it != g_scratch_tables.end()) g_scratch_tables.erase(it);
+            HIP_TRY(copy_table(base + l.jobs, sp->jobs, stream));
+            HIP_TRY(copy_table(base + l.groups, sp->groups, stream));
+            HIP_TRY(copy_table(base + l.items, sp->items, stream));
+            HIP_TRY(copy_table(base + l.mjobs, sp->mjobs, stream));
+            g_scratch_tables.emplace(dev, key);
+        }
+    }
+    const DevTables t{reinterpret_cast<const Job *>(base + l.jobs),
+                      reinterpret_cast<const LagGroup *>(base + l.groups),
+                      reinterpret_cast<const FinItem *>(base + l.items),
+                      reinterpret_cast<const MJob *>(base + l.mjobs), 1};
+    const Inst in = make_inst(*sp, A, lda, R, ldr, base + l.ws, o);
+    return rec_launch(*sp, t, in, stream);
 }
 
 // ------------------------------------------------------------ plain form ----
@@ -1071,6 +1171,22 @@ int covest_forward(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, vo
                    const covest_opts *opts, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     return covest_forward_ex(A, M, N, M, P, Q, R, P * Q, opts, ws, ws_bytes, stream);
+}
+
+int covest_forward_noalloc(const void *A, int64_t lda, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,
+                           int64_t ldr, const covest_opts *opts, hipStream_t stream)
+{
+    const covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (!A || !R) return fail(COVEST_ERR_INVALID_ARG, "A and R must be non-null device pointers");
+    if (lda < M) return fail(COVEST_ERR_INVALID_ARG, "lda (%lld) < M (%lld)", (long long)lda, (long long)M);
+    if (ldr < P * Q) return fail(COVEST_ERR_INVALID_ARG, "ldr (%lld) < PQ (%lld)", (long long)ldr, (long long)(P * Q));
+    if (!use_recurrence(o))
+        return fail(COVEST_ERR_UNSUPPORTED, "the no-allocation entry point runs the recurrence form only");
+    return rec_forward_noalloc(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, stream);
 }
 
 int covest_backward_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q,

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert cv.version() == 3
+    assert cv.version() == 4
 
 
 def _opts(**kw):
@@ -213,3 +213,27 @@ def test_backward_argument_errors_before_device_use():
     assert L.covest_backward(A, ctypes.c_void_p(base << 4), ctypes.c_void_p((base << 4) + dr_c64), 64, 64, 8, 8,
                              o32, None, need, None) == cv.ERR_WORKSPACE   # passes the overlap check
     assert L.covest_backward(A, G, A, 64, 64, 8, 8, None, ws, need, None) == cv.ERR_INVALID_ARG
+
+
+def test_noalloc_rejections_before_device_work():
+    """covest_forward_noalloc checks its arguments and the fixed scratch's
+    limit on the host; every case here returns before any device call."""
+    L = cv.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: each call is rejected first
+    assert L.covest_forward_noalloc(None, 64, 64, 64, 8, 8, fake, 64, None, None) == cv.ERR_INVALID_ARG
+    assert L.covest_forward_noalloc(fake, 63, 64, 64, 8, 8, fake, 64, None, None) == cv.ERR_INVALID_ARG
+    assert L.covest_forward_noalloc(fake, 64, 64, 64, 8, 8, fake, 63, None, None) == cv.ERR_INVALID_ARG
+    assert L.covest_forward_noalloc(fake, 64, 64, 64, 65, 8, fake, 520, None, None) == cv.ERR_SHAPE
+    assert L.covest_forward_noalloc(fake, 64, 64, 64, 8, 8, fake, 64, _opts(form="hankel", precision="fp32"),
+                                    None) == cv.ERR_UNSUPPORTED
+    assert L.covest_forward_noalloc(fake, 64, 64, 64, 8, 8, fake, 64, _opts(precision="bf16"),
+                                    None) == cv.ERR_UNSUPPORTED
+    # tables plus workspace beyond the 32 MiB array
+    assert L.covest_forward_noalloc(fake, 4096, 4096, 4096, 64, 64, fake, 4096, None, None) == cv.ERR_WORKSPACE
+    assert "scratch" in L.covest_last_error().decode()
+    n = ctypes.c_size_t(0)
+    assert L.covest_workspace_size(4096, 4096, 64, 64, None, ctypes.byref(n)) == cv.OK
+    assert n.value > (32 << 20)
+    # the headline shape fits
+    assert L.covest_workspace_size(1024, 1024, 32, 32, None, ctypes.byref(n)) == cv.OK
+    assert n.value < (32 << 20) - (1 << 20)
