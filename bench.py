@@ -498,11 +498,13 @@ def main():
             torch.cuda.synchronize()
             rk = covest.timing_read()
             covest.timing_enable(False)
-            kms = rk["hankel_main"][1] / rk["hankel_main"][0]
+            kname = "hankel_main" if prec == "fp32" else "hankel_main16"
+            kms = rk[kname][1] / rk[kname][0]
+            steps_ms = {k: v[1] / v[0] for k, v in rk.items() if k.startswith("hankel")}
             f_mfma = passes * 8.0 * cnt["K"] * cnt["eta"]
             gpu_results["plain_" + prec] = Rp.cpu().numpy()
             plain[prec] = {"ms_per_matrix": ms, "matrices_per_s": 1e3 / ms,
-                           "hankel_main_ms": kms,
+                           "hankel_main_ms": kms, "kernels_ms": steps_ms,
                            "mfma_tflops": f_mfma / (kms * 1e-3) / 1e12,
                            "mfma_frac": f_mfma / (kms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[peak_key]}
             print(f"[bench] plain {prec}: {ms:.3f} ms/matrix", file=sys.stderr, flush=True)

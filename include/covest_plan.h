@@ -76,6 +76,24 @@ typedef struct {
 int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
                          covest_mfma_plan_info *out, int32_t *jobs, int32_t *items);
 
+/* Plan of the plain form's 16-bit matrix-core path (prec: COVEST_PREC_BF16X3,
+ * _FP16X3, _BF16 or _FP16) for n_cu compute units.  A is first split into
+ * npl packed planes of N rows with row stride ldp; each item sums the
+ * positions [p0, p1) x [q0, q1) of one tm x tn output tile, staging pb
+ * position rows x qb position columns of A at a time in LDS (row strides
+ * stride_a and stride_b); tile t adds the partial tiles of the items listed
+ * in item_index[item0 .. item1); one workgroup runs each item.  Rows:
+ * items 6 int32 each (tr, tc, p0, p1, q0, q1), tiles 4 int32 each (tr, tc,
+ * item0, item1).  Arrays may be null.  COVEST_ERR_UNSUPPORTED for FP64 or
+ * FP32 (FP32 keeps 64 x 64 tiles). */
+typedef struct {
+    int32_t pb, qb, stride_a, stride_b, tm, tn, npl, ldp;
+    int32_t n_items, n_tiles, n_index;
+    int64_t lds, ws_bytes, planes_bytes;
+} covest_hankel_plan_info;
+int covest_hankel_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t prec, int32_t n_cu,
+                           covest_hankel_plan_info *out, int32_t *items, int32_t *tiles, int32_t *item_index);
+
 /* The engine COVEST_ENGINE_AUTO picks for one problem (batch = 0) or for a
  * problem of a batched plan (batch = 1): *engine = COVEST_ENGINE_VECTOR or
  * COVEST_ENGINE_MATRIX.  *fits = 1 when the matrix-core engine can run the

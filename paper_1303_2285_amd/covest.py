@@ -87,6 +87,12 @@ class covest_mfma_plan_info(ctypes.Structure):
                                               "fin_products")]
 
 
+class covest_hankel_plan_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("pb", "qb", "stride_a", "stride_b", "tm", "tn", "npl", "ldp",
+                                               "n_items", "n_tiles", "n_index")] + \
+               [(n, ctypes.c_int64) for n in ("lds", "ws_bytes", "planes_bytes")]
+
+
 # Every symbol the headers declare, with its ctypes signature.
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
@@ -129,6 +135,8 @@ SIGNATURES = {
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "covest_mfma_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
                                     ctypes.POINTER(covest_mfma_plan_info), ctypes.c_void_p, ctypes.c_void_p]),
+    "covest_hankel_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(covest_hankel_plan_info), _vp, _vp, _vp]),
     "covest_engine_choice": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]),
 }
@@ -543,6 +551,21 @@ def mfma_plan(N, M, P, Q, n_cu=256):
     _check(lib().covest_mfma_plan_get(N, M, P, Q, n_cu, ctypes.byref(info), jobs.ctypes.data,
                                       items.ctypes.data))
     return d, jobs, items
+
+
+def hankel_plan(N, M, P, Q, precision, n_cu=256):
+    """(info, items[n,6], tiles[n,4], item_index) of the 16-bit plain-form plan (host only)."""
+    import numpy as np
+    info = covest_hankel_plan_info()
+    prec = PRECS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().covest_hankel_plan_get(N, M, P, Q, prec, n_cu, ctypes.byref(info), None, None, None))
+    d = {name: getattr(info, name) for name, _ in covest_hankel_plan_info._fields_}
+    items = np.zeros((d["n_items"], 6), dtype=np.int32)
+    tiles = np.zeros((d["n_tiles"], 4), dtype=np.int32)
+    index = np.zeros(d["n_index"], dtype=np.int32)
+    _check(lib().covest_hankel_plan_get(N, M, P, Q, prec, n_cu, ctypes.byref(info), items.ctypes.data,
+                                        tiles.ctypes.data, index.ctypes.data))
+    return d, items, tiles, index
 
 
 def engine_choice(N, M, P, Q, batch=False):

@@ -452,6 +452,7 @@ struct DevHankel {
     HankelPlan hp;
     HItem *d_items = nullptr;
     HTile *d_tiles = nullptr;
+    int *d_item_index = nullptr;
 };
 std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<DevHankel>> g_hplans;
 
@@ -493,6 +494,7 @@ int get_hankel_plan(int N, int M, int P, int Q, int prec, DevHankel **out)
     dh->hp = make_hankel_plan(N, M, P, Q, prec, cu_count(dev));
     HIP_TRY(upload(&dh->d_items, dh->hp.items));
     HIP_TRY(upload(&dh->d_tiles, dh->hp.tiles));
+    HIP_TRY(upload(&dh->d_item_index, dh->hp.item_index));
     *out = dh.get();
     g_hplans.emplace(key, std::move(dh));
     return COVEST_OK;
@@ -527,11 +529,27 @@ int hankel_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void 
     ha.stride_b = hp.stride_b;
     ha.items = dh->d_items;
     ha.tiles = dh->d_tiles;
-    ha.partial = static_cast<double *>(ws);
     ha.R = R;
     ha.ldr = ldr;
     ha.fill_full = o.fill == COVEST_FILL_FULL ? 1 : 0;
     ha.normalize = o.normalize ? 1 : 0;
+    if (prec != kPrecF32) {
+        ha.planes = static_cast<const unsigned int *>(ws);
+        ha.ldp = hp.ldp;
+        ha.plane_elems = (int64_t)N * hp.ldp;
+        ha.partial32 = reinterpret_cast<float2 *>(static_cast<char *>(ws) + hp.planes_bytes);
+        ha.tn = hp.tn;
+        ha.item_index = dh->d_item_index;
+        HIP_TRY(timed("hankel_split", stream, [&] { return launch_hankel_split(ha, prec, stream); }));
+        HIP_TRY(timed("hankel_main16", stream, [&] {
+            return launch_hankel_main16(ha, prec, (int)hp.items.size(), hp.lds, stream);
+        }));
+        HIP_TRY(timed("hankel_reduce16", stream, [&] {
+            return launch_hankel_reduce16(ha, (int)hp.tiles.size(), stream);
+        }));
+        return finish_call(stream);
+    }
+    ha.partial = static_cast<double *>(ws);
     HIP_TRY(timed("hankel_main", stream, [&] {
         return launch_hankel_main(ha, prec, (int)hp.items.size(), hp.lds, stream);
     }));
@@ -1508,6 +1526,50 @@ int covest_timing_read(covest_timing_record *out, int cap)
 }
 
 }  // extern "C"
+
+extern "C" int covest_hankel_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t prec, int32_t n_cu,
+                                      covest_hankel_plan_info *out, int32_t *items, int32_t *tiles,
+                                      int32_t *item_index)
+{
+    if (!out) return fail(COVEST_ERR_INVALID_ARG, "out is null");
+    int st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (P > kMaxWindow || Q > kMaxWindow)
+        return fail(COVEST_ERR_UNSUPPORTED, "the matrix-core form supports P, Q <= %d", kMaxWindow);
+    if (prec < COVEST_PREC_FP64 || prec > COVEST_PREC_FP16) return fail(COVEST_ERR_INVALID_ARG, "unknown precision");
+    const int hp_prec = hankel_prec((covest_precision)prec);
+    if (hp_prec < 0 || hp_prec == kPrecF32)
+        return fail(COVEST_ERR_UNSUPPORTED, "the 16-bit plan covers BF16X3, FP16X3, BF16 and FP16");
+    const HankelPlan hp = make_hankel_plan((int)N, (int)M, (int)P, (int)Q, hp_prec, n_cu > 0 ? n_cu : 256);
+    out->pb = hp.pb;
+    out->qb = hp.qb;
+    out->stride_a = hp.stride_a;
+    out->stride_b = hp.stride_b;
+    out->tm = hp.tm;
+    out->tn = hp.tn;
+    out->npl = hp.npl16;
+    out->ldp = hp.ldp;
+    out->n_items = (int32_t)hp.items.size();
+    out->n_tiles = (int32_t)hp.tiles.size();
+    out->n_index = (int32_t)hp.item_index.size();
+    out->lds = (int64_t)hp.lds;
+    out->ws_bytes = (int64_t)hp.ws_bytes;
+    out->planes_bytes = (int64_t)hp.planes_bytes;
+    if (items)
+        for (size_t i = 0; i < hp.items.size(); ++i) {
+            const HItem &x = hp.items[i];
+            const int32_t row[6] = {x.tr, x.tc, x.p0, x.p1, x.q0, x.q1};
+            std::memcpy(items + 6 * i, row, sizeof(row));
+        }
+    if (tiles)
+        for (size_t t = 0; t < hp.tiles.size(); ++t) {
+            const HTile &x = hp.tiles[t];
+            const int32_t row[4] = {x.tr, x.tc, x.item0, x.item1};
+            std::memcpy(tiles + 4 * t, row, sizeof(row));
+        }
+    if (item_index) std::memcpy(item_index, hp.item_index.data(), hp.item_index.size() * sizeof(int32_t));
+    return ok();
+}
 
 extern "C" int covest_engine_choice(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t batch, int32_t *engine,
                                     int32_t *fits)

@@ -478,8 +478,152 @@ static int planes_of(int prec)
 // of the 16-bit forms.)
 static int pad_stride(int w) { return w + ((1 - w) % 32 + 32) % 32; }
 
+// LDS row stride of a staged rectangle read by 32 lanes at once: at least w,
+// and, among the next 32 values, the one that spreads the lanes of every
+// 32-row fragment of the tile rows [k_lo, k_lo + rows) over the most banks
+// (lane m reads row k % P, column k / P of the rectangle, k = k_lo + 32f + m).
+static int bank_stride(int w, int P, int PQ, int k_lo_step, int rows)
+{
+    int best = w, best_cost = 1 << 30;
+    for (int s = w; s < w + 32; ++s) {
+        int cost = 0;
+        for (int k0 = 0; k0 < PQ; k0 += 32) {
+            const int lo = (k0 / k_lo_step) * k_lo_step;   // first row of the tile holding k0
+            int hits[32] = {0};
+            int worst = 0;
+            for (int m = 0; m < 32 && k0 + m < PQ && k0 + m < lo + rows; ++m) {
+                const int k = k0 + m;
+                const int b = ((k % P) * s + (k / P - lo / P)) & 31;
+                worst = std::max(worst, ++hits[b]);
+            }
+            cost += worst;
+        }
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = s;
+        }
+    }
+    return best;
+}
+
+// 16-bit forms (B1-B3): A is split once into packed planes, workgroups own
+// 128 x 128 tiles (128 x 64 for FP16x3, whose cross terms keep accumulators of
+// their own), each item sums at most kItemPositions16 positions in FP32.
+static HankelPlan make_hankel_plan16(int N, int M, int P, int Q, int prec, int n_cu)
+{
+    HankelPlan hp;
+    hp.N = N; hp.M = M; hp.P = P; hp.Q = Q; hp.prec = prec;
+    const int PQ = P * Q, Kr = N - P + 1, Kc = M - Q + 1;
+    const bool split = prec == kPrecBF16x3 || prec == kPrecF16x3;
+    hp.npl16 = split ? 2 : 1;
+    hp.tm = 128;
+    hp.tn = prec == kPrecF16x3 ? 64 : 128;
+    // output tiles meeting the upper triangle
+    std::vector<std::pair<int, int>> tiles;
+    for (int tr = 0; tr < PQ; tr += hp.tm)
+        for (int tc = 0; tc < PQ; tc += hp.tn)
+            if (tc + hp.tn - 1 >= tr) tiles.push_back({tr, tc});
+    // widest column window of a tile's rows, per side
+    auto span_of = [&](int rows) {
+        int span = 0;
+        for (int lo = 0; lo < PQ; lo += rows)
+            span = std::max(span, std::min(Q - 1, std::min(PQ - 1, lo + rows - 1) / P) - lo / P);
+        return span;
+    };
+    const int span_a = span_of(hp.tm), span_b = span_of(hp.tn);
+    // item geometry: rows of positions x a column range, at most
+    // kItemPositions16 positions, and at least ~4 items per workgroup slot
+    int rows_item, cols_item;
+    if (Kc <= kItemPositions16) {
+        // Items of equal rows, one workgroup each, two resident per CU.  The
+        // split count S (items per tile) minimises rounds of workgroups times
+        // the rows of one item plus a halo allowance (the P - 1 extra rows every
+        // staged sub-block reads, worth ~4 rows of compute), so that the last
+        // round is not left half empty.
+        cols_item = Kc;
+        const int rows_max = std::max(1, std::min(Kr, kItemPositions16 / Kc));
+        const int64_t slots = 2LL * std::max(1, n_cu);
+        const int64_t nt = (int64_t)tiles.size();
+        const int s_lo = (Kr + rows_max - 1) / rows_max;
+        const int s_hi = std::min<int64_t>(Kr, std::max<int64_t>(s_lo, 16 * slots / nt + 1));
+        double best_t = 1e300;
+        rows_item = rows_max;
+        for (int S = s_lo; S <= s_hi; ++S) {
+            const int r = (Kr + S - 1) / S;
+            const int64_t n = nt * ((Kr + r - 1) / r);
+            const double t = (double)((n + slots - 1) / slots) * (r + 4.0);
+            if (t < best_t - 1e-9) {
+                best_t = t;
+                rows_item = r;
+            }
+        }
+    } else {
+        rows_item = 1;
+        cols_item = kItemPositions16;
+    }
+    // sub-tile: the most positions per staged word within the LDS budget
+    const size_t budget = 76 * 1024;
+    double best = -1.0;
+    for (int qb : {32, 64, 96, 128, 192, 256}) {
+        if (qb > ((cols_item + 7) / 8) * 8 && qb != 32) continue;
+        // a row holds the sub-block's columns plus the 16 words that the last
+        // step and the next step's early reads may touch past them
+        const int s_a = bank_stride(qb + span_a + 16, P, PQ, hp.tm, hp.tm);
+        const int s_b = bank_stride(qb + span_b + 16, P, PQ, hp.tn, hp.tn);
+        for (int pb = 1; pb <= rows_item; ++pb) {
+            const size_t bytes = (size_t)hp.npl16 * (pb + P) * (s_a + s_b) * 4;
+            if (bytes > budget) break;
+            const double eff = (double)pb * std::min(qb, cols_item) / ((double)(pb + P) * (s_a + s_b));
+            if (eff > best) {
+                best = eff;
+                hp.pb = pb;
+                hp.qb = qb;
+                hp.stride_a = s_a;
+                hp.stride_b = s_b;
+                hp.lds = bytes;
+            }
+        }
+    }
+    if (hp.pb == 0) {
+        hp.pb = 1;
+        hp.qb = 32;
+        hp.stride_a = bank_stride(32 + span_a + 16, P, PQ, hp.tm, hp.tm);
+        hp.stride_b = bank_stride(32 + span_b + 16, P, PQ, hp.tn, hp.tn);
+        hp.lds = (size_t)hp.npl16 * (1 + P) * (hp.stride_a + hp.stride_b) * 4;
+    }
+    // items ordered by position range, then tile: neighbouring items read the
+    // same rows of A (the kernel gives each XCD a contiguous range of items)
+    std::vector<std::vector<int>> of_tile(tiles.size());
+    for (int p0 = 0; p0 < Kr; p0 += rows_item) {
+        const int p1 = std::min(Kr, p0 + rows_item);
+        for (int q0 = 0; q0 < Kc; q0 += cols_item) {
+            const int q1 = std::min(Kc, q0 + cols_item);
+            for (size_t t = 0; t < tiles.size(); ++t) {
+                of_tile[t].push_back((int)hp.items.size());
+                hp.items.push_back({tiles[t].first, tiles[t].second, p0, p1, q0, q1});
+            }
+        }
+    }
+    // the reduction reads each tile's items through an index list (item0 .. item1
+    // of `order`); items stay in position order, so the FP64 sum order is fixed
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        HTile ht{tiles[t].first, tiles[t].second, (int)hp.item_index.size(), 0};
+        hp.item_index.insert(hp.item_index.end(), of_tile[t].begin(), of_tile[t].end());
+        ht.item1 = (int)hp.item_index.size();
+        hp.tiles.push_back(ht);
+    }
+    // staging reads whole 64-column chunks of a row: pad the planes' rows so
+    // that every chunk stays inside them
+    hp.ldp = M + 64 * ((hp.qb + std::max(span_a, span_b) + 63) / 64) + 64;
+    const size_t plane_bytes = (size_t)hp.npl16 * N * hp.ldp * 4;
+    hp.planes_bytes = (plane_bytes + 255) / 256 * 256;
+    hp.ws_bytes = hp.planes_bytes + hp.items.size() * (size_t)hp.tm * hp.tn * 8;
+    return hp;
+}
+
 HankelPlan make_hankel_plan(int N, int M, int P, int Q, int prec, int n_cu)
 {
+    if (prec != kPrecF32) return make_hankel_plan16(N, M, P, Q, prec, n_cu);
     HankelPlan hp;
     hp.N = N; hp.M = M; hp.P = P; hp.Q = Q; hp.prec = prec;
     const int PQ = P * Q, Kr = N - P + 1, Kc = M - Q + 1;
@@ -524,7 +668,7 @@ HankelPlan make_hankel_plan(int N, int M, int P, int Q, int prec, int n_cu)
             HTile t{64 * a, 64 * b, (int)hp.items.size(), 0};
             for (int s = 0; s < splits; ++s) {
                 const int p0 = (int)((int64_t)s * Kr / splits), p1 = (int)((int64_t)(s + 1) * Kr / splits);
-                if (p1 > p0) hp.items.push_back({64 * a, 64 * b, p0, p1});
+                if (p1 > p0) hp.items.push_back({64 * a, 64 * b, p0, p1, 0, Kc});
             }
             t.item1 = (int)hp.items.size();
             hp.tiles.push_back(t);

@@ -78,7 +78,13 @@ struct HankelPlan {
     std::vector<HItem> items;
     std::vector<HTile> tiles;
     size_t lds = 0;
-    size_t ws_bytes = 0;     // FP64 partial tiles
+    size_t ws_bytes = 0;     // FP32: FP64 partial tiles; 16-bit: planes + FP32 partial tiles
+    // 16-bit forms
+    int tm = 64, tn = 64;    // tile rows and columns
+    int npl16 = 0;           // packed planes of A (1 plain, 2 split)
+    int ldp = 0;             // plane row stride (elements)
+    size_t planes_bytes = 0; // offset of the partial tiles in the workspace
+    std::vector<int> item_index;   // tile t sums items item_index[tiles[t].item0 .. item1)
 };
 
 // n_cu: compute units of the device (work items are sized for ~8 per CU).

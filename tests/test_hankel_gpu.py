@@ -108,19 +108,20 @@ def test_edge_integer_exact(cv, torch_dev, oracle_mod, shape):
     N, M, P, Q = shape
     A = synth.small_int(N, M, seed=N * 7 + M * 3 + P)
     _note("hankel edge", shape)
-    for prec in ("fp32", "bf16x3"):
+    for prec in PRECS:
         C = hankel(cv, torch_dev, A, P, Q, prec, normalize=False)
         ref = oracle_mod.forward(A, P, Q, normalize=False)
         assert np.array_equal(C.astype(np.complex128), ref), prec
 
 
-def test_fill_upper(cv, torch_dev, oracle_mod):
+@pytest.mark.parametrize("prec", PRECS)
+def test_fill_upper(cv, torch_dev, oracle_mod, prec):
     torch, dev = torch_dev
     A = synth.small_int(40, 44, seed=12)
     P, Q = 5, 6
     out = torch.full((P * Q, P * Q), complex(3.0, 4.0), dtype=torch.complex64, device=dev)
-    _note("hankel fill upper")
-    cv.covest_forward(torch.from_numpy(A).to(dev), P, Q, form="hankel", precision="fp32",
+    _note("hankel fill upper", prec)
+    cv.covest_forward(torch.from_numpy(A).to(dev), P, Q, form="hankel", precision=prec,
                       fill="upper", normalize=False, out=out)
     torch.cuda.synchronize()
     R = out.cpu().numpy().astype(np.complex128)
@@ -129,6 +130,32 @@ def test_fill_upper(cv, torch_dev, oracle_mod):
     il = np.tril_indices(P * Q, -1)
     assert np.array_equal(R[iu], ref[iu])
     assert np.all(R[il] == complex(3.0, 4.0))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3", "fp16", "fp16x3"])
+def test_long_rows_integer_exact(cv, torch_dev, oracle_mod, prec):
+    """Rows of more positions than one item sums (16384): items split along
+    the row; integer input, exact."""
+    A = synth.small_int(6, 17000, seed=31)
+    P, Q = 3, 5
+    _note("hankel long rows", prec)
+    C = hankel(cv, torch_dev, A, P, Q, prec, normalize=False)
+    ref = oracle_mod.forward(A, P, Q, normalize=False, threads=oracle_mod.max_threads())
+    assert np.array_equal(C.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3", "fp16", "fp16x3"])
+def test_strided_input(cv, torch_dev, oracle_mod, prec):
+    """A strided view of A (lda > M) through the split pass."""
+    torch, dev = torch_dev
+    full = synth.small_int(90, 120, seed=32)
+    P, Q = 7, 9
+    _note("hankel strided", prec)
+    At = torch.from_numpy(full).to(dev)[:, 5:105]
+    C = cv.covest_forward(At, P, Q, form="hankel", precision=prec, normalize=False)
+    torch.cuda.synchronize()
+    ref = oracle_mod.forward(full[:, 5:105], P, Q, normalize=False)
+    assert np.array_equal(C.cpu().numpy().astype(np.complex128), ref)
 
 
 def test_fp64_not_offered(cv, torch_dev):
