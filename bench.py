@@ -70,6 +70,9 @@ def parse():
                     help="skip the comparison run of the recurrence on the vector engine")
     ap.add_argument("--worker-scaling", action="store_true",
                     help="only run the worker-count study (Sec. 5.1, Fig. 4 sizes) and print its table")
+    ap.add_argument("--cu-study", action="store_true",
+                    help="only run the compute-unit scaling and per-combination cost study "
+                         "(Sec. 5.1, Figs. 4-5, the paper's sizes) and print its table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 256 MiB (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
@@ -372,6 +375,121 @@ def worker_scaling():
     print(json.dumps({"study": "worker scaling", "rows": rows}), flush=True)
 
 
+def _hip_runtime():
+    """The HIP runtime torch already loaded (one runtime per process)."""
+    import ctypes
+    for line in open("/proc/self/maps"):
+        if "libamdhip64.so" in line:
+            return ctypes.CDLL(line.split()[-1])
+    raise RuntimeError("libamdhip64 is not loaded")
+
+
+def cu_study():
+    """The paper's scaling study on the GPU (Sec. 5.1, Figs. 4-5) at its own
+    sizes: 20 x 20 input with an 8 x 8 window (113 combinations) and 32 x 32
+    with 13 x 13 (313), as one matrix, as 2 matrices (the paper's 626
+    combinations) and as 64.  Speedup against active compute units: every call
+    runs on a stream whose CU mask enables the first n CUs (n = 1 ... 256), HIP
+    events on that stream, median of 30 calls.  Per-combination cost: every
+    finalize workgroup (one unique combination, the paper's unit of work) of
+    one call on the whole GPU stamps the device's 100 MHz wall clock at its
+    start and end; the sorted durations are the Fig. 5 analog."""
+    import ctypes
+    import numpy as np
+    os.environ["COVEST_TUNE"] = "0"     # the same plans at every CU count
+    import torch
+    from paper_1303_2285_amd import covest, synth
+    dev = torch.device("cuda:0")
+    torch.zeros(1, device=dev)
+    hip = _hip_runtime()
+    hip.hipExtStreamCreateWithCUMask.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                                 ctypes.POINTER(ctypes.c_uint32)]
+    hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+    n_cu_dev = torch.cuda.get_device_properties(dev).multi_processor_count
+    words = (n_cu_dev + 31) // 32
+    out = {"study": "CU scaling and per-combination cost", "device_cus": n_cu_dev, "scaling": [], "costs": []}
+    cases = [(20, 20, 8, 8, 1), (32, 32, 13, 13, 1), (32, 32, 13, 13, 2), (32, 32, 13, 13, 64)]
+    # masks the runtime refuses (on MI355X: fewer CUs than XCDs) are recorded and skipped
+    cu_list, refused = [], []
+    for c in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+        if c > n_cu_dev:
+            continue
+        mask = (ctypes.c_uint32 * words)()
+        for b in range(c):
+            mask[b // 32] |= 1 << (b % 32)
+        hs = ctypes.c_void_p(0)
+        if hip.hipExtStreamCreateWithCUMask(ctypes.byref(hs), words, mask) == 0:
+            hip.hipStreamDestroy(hs)
+            cu_list.append(c)
+        else:
+            refused.append(c)
+            hip.hipGetLastError()   # clear the refusal, or the next HIP call reports it
+    torch.cuda.synchronize()
+    out["refused_cu_counts"] = refused
+    for (n, m, p, q, copies) in cases:
+        As = [torch.from_numpy(synth.gaussian(n, m, seed=2000 + i)).to(dev) for i in range(copies)]
+        row = {"N": n, "M": m, "P": p, "Q": q, "matrices": copies,
+               "combinations": copies * covest.counts(n, m, p, q)["n_uc"], "cus": [], "ms": []}
+        for ncu in cu_list:
+            mask = (ctypes.c_uint32 * words)()
+            for b in range(ncu):
+                mask[b // 32] |= 1 << (b % 32)
+            hs = ctypes.c_void_p(0)
+            rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(hs), words, mask)
+            if rc != 0:
+                raise RuntimeError(f"hipExtStreamCreateWithCUMask returned {rc}")
+            stream = torch.cuda.ExternalStream(hs.value, device=dev)
+            with torch.cuda.stream(stream):
+                if copies == 1:
+                    Rout = torch.empty((p * q, p * q), dtype=torch.complex128, device=dev)
+                    ws = torch.empty(max(1, covest.workspace_size(n, m, p, q)), dtype=torch.uint8, device=dev)
+                    run = lambda: covest.covest_forward(As[0], p, q, out=Rout, workspace=ws)
+                else:
+                    plan = covest.BatchedPlan([(A, p, q) for A in As])
+                    run = plan.run
+                for _ in range(3):
+                    run()
+                ts = []
+                for _ in range(30):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    run()
+                    b.record(stream)
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                if copies > 1:
+                    plan.close()
+            stream.synchronize()
+            hip.hipStreamDestroy(hs)
+            ts.sort()
+            row["cus"].append(ncu)
+            row["ms"].append(ts[len(ts) // 2])
+            print(f"[cu-study] {n}x{m}/{p}x{q} x{copies}: {ncu} CUs {ts[len(ts) // 2]:.4f} ms",
+                  file=sys.stderr, flush=True)
+        out["scaling"].append(row)
+    for (n, m, p, q) in [(20, 20, 8, 8), (32, 32, 13, 13)]:
+        A = torch.from_numpy(synth.gaussian(n, m, seed=2000)).to(dev)
+        for _ in range(3):
+            covest.covest_forward_stamped(A, p, q)
+        torch.cuda.synchronize()
+        R, stamps, items = covest.covest_forward_stamped(A, p, q)
+        torch.cuda.synchronize()
+        st = stamps.cpu().numpy().astype(np.int64)
+        dur_us = (st[:, 1] - st[:, 0]) * 0.01
+        prods = np.array([(n - abs(int(dr))) * (m - abs(int(dc))) for (_, dr, dc, _, _) in items])
+        order = np.argsort(dur_us)
+        out["costs"].append({"N": n, "M": m, "P": p, "Q": q, "combinations": int(len(dur_us)),
+                             "sorted_us": [round(float(x), 2) for x in dur_us[order]],
+                             "products_of_sorted": [int(x) for x in prods[order]],
+                             "corr_duration_products": float(np.corrcoef(dur_us, prods)[0, 1])
+                             if np.std(dur_us) > 0 else None,
+                             "span_us": float((st[:, 1].max() - st[:, 0].min()) * 0.01)})
+        print(f"[cu-study] costs {n}x{m}/{p}x{q}: {len(dur_us)} combinations, min {dur_us.min():.2f} us, "
+              f"median {np.median(dur_us):.2f} us, max {dur_us.max():.2f} us", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -381,6 +499,9 @@ def main():
         sys.exit(2)
     if args.worker_scaling:
         worker_scaling()
+        return
+    if args.cu_study:
+        cu_study()
         return
     if args.copy_calibration:
         copy_calibration()

@@ -1,6 +1,7 @@
 /*
- * covest_plan.h -- host-only introspection of libcovest's recurrence plan,
- * for tests and tools.  No device is needed.
+ * covest_plan.h -- introspection of libcovest's plans for tests and tools
+ * (host only, no device needed), and one measurement call
+ * (covest_forward_stamped) that times every finalize item on the device.
  *
  * The recurrence (Sec. 3.3 of the paper: each product is computed once and
  * every output entry has a single writer) splits the products of every unique
@@ -18,7 +19,11 @@
 #ifndef COVEST_PLAN_H
 #define COVEST_PLAN_H
 
+#include <stddef.h>
 #include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#include "covest.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -75,6 +80,20 @@ typedef struct {
  * COVEST_ERR_UNSUPPORTED when the engine cannot run the shape. */
 int covest_mfma_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t n_cu,
                          covest_mfma_plan_info *out, int32_t *jobs, int32_t *items);
+
+/* Measurement run of the recurrence (covest_forward with lda = M, ldr = PQ):
+ * the same result, and for every finalize item -- one unique combination
+ * (dr, dc), the work unit the paper assigns to a core (Sec. 3.4, 5.1, Fig. 5)
+ * -- the device's constant 100 MHz wall clock when its workgroup started and
+ * when it ended: stamps[2i], stamps[2i+1] (device memory, n_stamps >= 2 x the
+ * number of items, which is covest_counts' n_uc).  If items is non-null
+ * (host, 5 int32 per item: inst, dr, dc, bulk0, bulk1) it receives the items
+ * in stamp order.  The stamps cost one branch per workgroup; every other
+ * entry point passes none.  Errors as covest_forward, plus
+ * COVEST_ERR_INVALID_ARG for too few stamps. */
+int covest_forward_stamped(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,
+                           const covest_opts *opts, void *ws, size_t ws_bytes, uint64_t *stamps,
+                           int64_t n_stamps, int32_t *items, hipStream_t stream);
 
 /* Plan of the plain form's 16-bit matrix-core path (prec: COVEST_PREC_BF16X3,
  * _FP16X3, _BF16 or _FP16) for n_cu compute units.  A is first split into

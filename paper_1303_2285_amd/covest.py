@@ -135,6 +135,8 @@ SIGNATURES = {
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "covest_mfma_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32,
                                     ctypes.POINTER(covest_mfma_plan_info), ctypes.c_void_p, ctypes.c_void_p]),
+    "covest_forward_stamped": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, ctypes.POINTER(covest_opts), _vp,
+                                      ctypes.c_size_t, _vp, _i64, _vp, _vp]),
     "covest_hankel_plan_get": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(covest_hankel_plan_info), _vp, _vp, _vp]),
     "covest_engine_choice": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -551,6 +553,29 @@ def mfma_plan(N, M, P, Q, n_cu=256):
     _check(lib().covest_mfma_plan_get(N, M, P, Q, n_cu, ctypes.byref(info), jobs.ctypes.data,
                                       items.ctypes.data))
     return d, jobs, items
+
+
+def covest_forward_stamped(A, P: int, Q: int, *, engine="auto"):
+    """covest_forward (FP64) plus, per finalize item (one unique combination),
+    the 100 MHz wall clock at its workgroup's start and end.  Returns
+    (R, stamps[n_uc, 2] int64 on the device, items[n_uc, 5] int32 host:
+    inst, dr, dc, bulk0, bulk1).  A measurement call."""
+    import numpy as np
+    torch = _torch()
+    _check_input(A)
+    N, M = A.shape
+    o = make_opts("recurrence", "fp64", "full", True, 0, 0, engine)
+    n_uc = counts(N, M, P, Q)["n_uc"]
+    R = torch.empty((P * Q, P * Q), dtype=torch.complex128, device=A.device)
+    stamps = torch.zeros((n_uc, 2), dtype=torch.int64, device=A.device)
+    items = np.zeros((n_uc, 5), dtype=np.int32)
+    need = workspace_size(N, M, P, Q, form="recurrence", engine=engine)
+    ws, nbytes = _workspace(need, A.device)
+    _check(lib().covest_forward_stamped(
+        ctypes.c_void_p(A.data_ptr()), N, M, P, Q, ctypes.c_void_p(R.data_ptr()), ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), nbytes, ctypes.c_void_p(stamps.data_ptr()),
+        2 * n_uc, items.ctypes.data, _stream_handle(A.device)))
+    return R, stamps, items
 
 
 def hankel_plan(N, M, P, Q, precision, n_cu=256):

@@ -311,7 +311,8 @@ struct DevTables {
 
 // The recurrence's launches for one problem: main pass (matrix cores or
 // vector units), then the finalize.
-int rec_launch(const ShapePlan &sp, const DevTables &t, const Inst &in, hipStream_t stream)
+int rec_launch(const ShapePlan &sp, const DevTables &t, const Inst &in, hipStream_t stream,
+               unsigned long long *stamps = nullptr)
 {
     if (!sp.mjobs.empty()) {
         MfmaArgs ma{};
@@ -341,6 +342,7 @@ int rec_launch(const ShapePlan &sp, const DevTables &t, const Inst &in, hipStrea
     fa.n_items = (int)sp.items.size();
     fa.use_inline = 1;
     fa.inst_inline = in;
+    fa.stamps = stamps;
     HIP_TRY(timed("rec_finalize", stream, [&] {
         return launch_rec_finalize(fa, (int)sp.items.size(), sp.lds_fin, sp.fin_variant, stream);
     }));
@@ -348,7 +350,8 @@ int rec_launch(const ShapePlan &sp, const DevTables &t, const Inst &in, hipStrea
 }
 
 int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
-                const covest_opts &o, void *ws, size_t ws_bytes, hipStream_t stream)
+                const covest_opts &o, void *ws, size_t ws_bytes, hipStream_t stream,
+                unsigned long long *stamps = nullptr, int64_t n_stamps = 0)
 {
     int engine = 0;
     int st = rec_engine(N, M, P, Q, lda, o, &engine);
@@ -359,9 +362,12 @@ int rec_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R,
     const ShapePlan &sp = dp->sp;
     if (ws_bytes < sp.ws_bytes || (sp.ws_bytes > 0 && ws == nullptr))
         return fail(COVEST_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", sp.ws_bytes, ws_bytes);
+    if (stamps && n_stamps < 2 * (int64_t)sp.items.size())
+        return fail(COVEST_ERR_INVALID_ARG, "stamps hold %lld values, the finalize has %zu items (2 each)",
+                    (long long)n_stamps, sp.items.size());
     const Inst in = make_inst(sp, A, lda, R, ldr, ws, o);
     return rec_launch(sp, DevTables{dp->d_jobs, dp->d_groups, dp->d_items, dp->d_mjobs, dp->xcd_remap}, in,
-                      stream);
+                      stream, stamps);
 }
 
 // ------------------------------------------------------ fixed scratch ----
@@ -1526,6 +1532,33 @@ int covest_timing_read(covest_timing_record *out, int cap)
 }
 
 }  // extern "C"
+
+extern "C" int covest_forward_stamped(const void *A, int64_t N, int64_t M, int64_t P, int64_t Q, void *R,
+                                     const covest_opts *opts, void *ws, size_t ws_bytes, uint64_t *stamps,
+                                     int64_t n_stamps, int32_t *items, hipStream_t stream)
+{
+    const covest_opts o = resolve_opts(opts);
+    int st = check_opts(o);
+    if (st != COVEST_OK) return st;
+    st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (!A || !R || !stamps) return fail(COVEST_ERR_INVALID_ARG, "A, R and stamps must be non-null device pointers");
+    if (!use_recurrence(o)) return fail(COVEST_ERR_UNSUPPORTED, "stamps are taken for the recurrence form only");
+    st = rec_forward(A, M, (int)N, (int)M, (int)P, (int)Q, R, P * Q, o, ws, ws_bytes, stream,
+                     reinterpret_cast<unsigned long long *>(stamps), n_stamps);
+    if (st != COVEST_OK || !items) return st;
+    // the items in stamp order (host copy of the finalize table of the plan just used)
+    int engine = 0;
+    st = rec_engine((int)N, (int)M, (int)P, (int)Q, M, o, &engine);
+    if (st != COVEST_OK) return st;
+    const auto sp = host_plan((int)N, (int)M, (int)P, (int)Q, o.ring_cols, o.ring_rows, engine);
+    for (size_t i = 0; i < sp->items.size(); ++i) {
+        const FinItem &x = sp->items[i];
+        const int32_t row[5] = {x.inst, x.dr, x.dc, x.bulk0, x.bulk1};
+        std::memcpy(items + 5 * i, row, sizeof(row));
+    }
+    return ok();
+}
 
 extern "C" int covest_hankel_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t prec, int32_t n_cu,
                                       covest_hankel_plan_info *out, int32_t *items, int32_t *tiles,

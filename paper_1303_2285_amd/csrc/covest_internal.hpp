@@ -168,6 +168,8 @@ struct FinArgs {
     int n_items;
     int use_inline;
     Inst inst_inline;
+    unsigned long long *stamps;   // measurement runs only (else null): per item, the
+                                  // 100 MHz wall clock at its workgroup's start and end
 };
 
 }  // namespace covest

@@ -319,8 +319,28 @@ __device__ __forceinline__ void store_r(const Inst &in, int k1, int k2, double2 
     }
 }
 
+// Per-item timing of a measurement run (fa.stamps non-null): the constant
+// 100 MHz wall clock when the item's workgroup starts and when all its threads
+// are done, written by thread 0.  A null fa.stamps (every ordinary call)
+// skips both.
+struct ItemStamp {
+    unsigned long long t0;
+    __device__ explicit ItemStamp(const FinArgs &fa) : t0(fa.stamps ? wall_clock64() : 0ull) {}
+    __device__ void done(const FinArgs &fa, int idx) const
+    {
+        if (fa.stamps) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                fa.stamps[2 * idx] = t0;
+                fa.stamps[2 * idx + 1] = wall_clock64();
+            }
+        }
+    }
+};
+
 __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
 {
+    const ItemStamp stamp(fa);
     extern __shared__ double2 cs[];
     const FinItem it = fa.items[xcd_block(blockIdx.x, fa.n_items)];
     const Inst in = fa.use_inline ? fa.inst_inline : fa.insts[it.inst];
@@ -403,6 +423,7 @@ __global__ void __launch_bounds__(64) rec_finalize(FinArgs fa)
             }
         }
     }
+    stamp.done(fa, xcd_block(blockIdx.x, fa.n_items));
 }
 
 // s + t[lo·st] + t[(lo+1)·st] + ... + t[(hi−1)·st], added in index order.  The
@@ -433,6 +454,7 @@ __device__ __forceinline__ double2 lds_chain(double2 s, const double2 *t, int lo
 template <int kFinBatch, int kFinChunk>
 __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
 {
+    const ItemStamp stamp(fa);
     extern __shared__ double2 V[];
     __shared__ double2 red[256];
     __shared__ double2 zrs[kFinMaxRows];   // row-strip sums of the individual rows
@@ -609,6 +631,7 @@ __global__ void __launch_bounds__(256) rec_finalize_tab(FinArgs fa)
             }
         }
     }
+    stamp.done(fa, xcd_block(blockIdx.x, fa.n_items));
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave, in a fixed order: three
@@ -676,6 +699,7 @@ __device__ __forceinline__ double2 range_sum(double2 *row, double2 e, int lo, in
 template <bool INLINE, int KCLS>
 __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
 {
+    const ItemStamp stamp(fa);
     // classes per wave at most: 16 (1 + n_ir <= 64) or 8 (1 + n_ir <= 32, fewer
     // registers, so more workgroups per CU hide the loads of small tables)
     constexpr int kCls = KCLS;
@@ -778,6 +802,7 @@ __global__ void __launch_bounds__(256) rec_finalize_scan(FinArgs fa)
             store_r(in, i1 + P * b, (i1 + dr) + P * (b + dc), v, dr == 0 && dc == 0);
         }
     }
+    stamp.done(fa, xcd_block(blockIdx.x, fa.n_items));
 }
 
 #undef ZR

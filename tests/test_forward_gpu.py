@@ -269,3 +269,23 @@ def test_non_finite_input(cv, torch_dev, oracle_mod, shape, engine, bad):
     assert np.all(bad_gpu[bad_ref])
     fin = ~bad_gpu
     assert np.array_equal(R[fin], ref[fin])
+
+
+@pytest.mark.parametrize("shape", [(20, 20, 8, 8), (32, 32, 13, 13), (64, 64, 8, 8)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_stamped_forward(cv, torch_dev, shape):
+    """The measurement call: the same R as covest_forward, bit for bit, and one
+    start/end stamp per unique combination (eq. 3.4's set, each once)."""
+    torch, dev = torch_dev
+    N, M, P, Q = shape
+    A = torch.from_numpy(synth.gaussian(N, M, seed=77)).to(dev)
+    _note("stamped forward", shape)
+    R0 = cv.covest_forward(A, P, Q)
+    R1, stamps, items = cv.covest_forward_stamped(A, P, Q)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(R0), torch.view_as_real(R1))
+    st = stamps.cpu().numpy()
+    assert np.all(st[:, 0] > 0) and np.all(st[:, 1] >= st[:, 0])
+    lags = {(int(dr), int(dc)) for (_, dr, dc, _, _) in items}
+    uc = {(dr, 0) for dr in range(P)} | {(dr, dc) for dc in range(1, Q) for dr in range(-(P - 1), P)}
+    assert lags == uc and len(items) == len(uc) == cv.counts(N, M, P, Q)["n_uc"]
