@@ -615,13 +615,16 @@ struct covest_plan {
     covest_opts opts{};
     int64_t count = 0;
     hipStream_t own_stream = nullptr;
+    hipStream_t side_stream = nullptr;           // second branch of the captured graph
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Job *d_jobs = nullptr;
     LagGroup *d_groups = nullptr;
     Inst *d_insts = nullptr;
-    FinItem *d_items[kFinVariants] = {};   // per finalize variant (kFinTable, ...)
+    // finalize items per engine of their problem (0 vector, 1 matrix cores) and variant
+    FinItem *d_items[2][kFinVariants] = {};
     unsigned int *d_counter = nullptr;
     void *d_ws = nullptr;
-    int n_jobs = 0, n_items[kFinVariants] = {}, grid = 0;
+    int n_jobs = 0, n_items[2][kFinVariants] = {}, grid = 0;
     size_t lds_main = 0, lds_fin[kFinVariants] = {};
     // matrix-core jobs, one launch per lag-block shape (mt x nt tiles)
     struct MfmaLaunch {
@@ -646,11 +649,15 @@ void free_plan(covest_plan *p)
     void *bufs[] = {p->d_jobs, p->d_groups, p->d_insts, p->d_counter, p->d_ws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
-    for (FinItem *b : p->d_items)
-        if (b) (void)hipFree(b);
+    for (auto &per_engine : p->d_items)
+        for (FinItem *b : per_engine)
+            if (b) (void)hipFree(b);
     for (auto &l : p->mfma)
         if (l.d_jobs) (void)hipFree(l.d_jobs);
     if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+    if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     delete p;
 }
 
@@ -949,7 +956,7 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
     std::vector<double> jcost;
     std::vector<LagGroup> groups;
     std::vector<Inst> insts(count);
-    std::vector<FinItem> items[kFinVariants];
+    std::vector<FinItem> items[2][kFinVariants];   // [engine is matrix cores][variant]
     size_t ws_off = 0;
     std::vector<size_t> ws_base(count);
     std::vector<ShapePlan> plans(count);
@@ -997,7 +1004,7 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
         const int var = sp.fin_variant;
         for (FinItem it : sp.items) {
             it.inst = (int)i;
-            items[var].push_back(it);
+            items[engine[i] == 2][var].push_back(it);
         }
         if (engine[i] != 2) plan->lds_main = std::max(plan->lds_main, sp.lds_main);
         plan->lds_fin[var] = std::max(plan->lds_fin[var], sp.lds_fin);
@@ -1013,13 +1020,15 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
     for (size_t j : order) sorted.push_back(jobs[j]);
     plan->est_cost = total;
     plan->n_jobs = (int)sorted.size();
-    for (int v = 0; v < kFinVariants; ++v) plan->n_items[v] = (int)items[v].size();
+    for (int g = 0; g < 2; ++g)
+        for (int v = 0; v < kFinVariants; ++v) plan->n_items[g][v] = (int)items[g][v].size();
     plan->grid = std::max(1, std::min(resident, plan->n_jobs));
     if (const int cap = worker_cap()) plan->grid = std::min(plan->grid, cap);
     HIP_TRY(upload(&plan->d_jobs, sorted));
     HIP_TRY(upload(&plan->d_groups, groups));
     HIP_TRY(upload(&plan->d_insts, insts));
-    for (int v = 0; v < kFinVariants; ++v) HIP_TRY(upload(&plan->d_items[v], items[v]));
+    for (int g = 0; g < 2; ++g)
+        for (int v = 0; v < kFinVariants; ++v) HIP_TRY(upload(&plan->d_items[g][v], items[g][v]));
     HIP_TRY(hipMalloc(&plan->d_counter, 256));
     for (auto &kv : mgroups) {
         // longest first: the hardware hands out workgroups in block order
@@ -1045,9 +1054,24 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
         HIP_TRY(hipStreamCreateWithFlags(&plan->own_stream, hipStreamNonBlocking));
         cs = plan->own_stream;
     }
+    // The vector kernel and the matrix-core launches touch disjoint problems:
+    // they are two branches of the graph, joined before the finalize, so that
+    // one fills the CUs the other's tail leaves idle.
+    const bool branch = plan->n_jobs > 0 && !plan->mfma.empty();
+    if (branch) {
+        HIP_TRY(hipStreamCreateWithFlags(&plan->side_stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&plan->ev_join, hipEventDisableTiming));
+    }
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    if (plan->n_jobs > 0) {
+    hipStream_t ms = cs;
+    if (branch) {
+        e = hipEventRecord(plan->ev_fork, cs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(plan->side_stream, plan->ev_fork, 0);
+        ms = plan->side_stream;
+    }
+    if (e == hipSuccess && plan->n_jobs > 0) {
         MainArgs ma{};
         ma.jobs = plan->d_jobs;
         ma.groups = plan->d_groups;
@@ -1063,16 +1087,24 @@ int build_batched(covest_plan *plan, const covest_problem_ex *pr, int64_t count,
         ma.n_jobs = l.n_jobs;
         ma.xcd_remap = 0;
         ma.insts = plan->d_insts;
-        e = launch_rec_mfma(ma, l.mt, l.nt, l.n_jobs, l.lds, cs);
+        e = launch_rec_mfma(ma, l.mt, l.nt, l.n_jobs, l.lds, ms);
     }
-    for (int v = 0; v < kFinVariants && e == hipSuccess; ++v) {
-        if (plan->n_items[v] == 0) continue;
-        FinArgs fa{};
-        fa.items = plan->d_items[v];
-        fa.insts = plan->d_insts;
-        fa.n_items = plan->n_items[v];
-        fa.use_inline = 0;
-        e = launch_rec_finalize(fa, plan->n_items[v], plan->lds_fin[v], v, cs);
+    // each engine's finalize follows its own main pass, on its own branch
+    for (int g = 0; g < 2; ++g) {
+        hipStream_t fs = g == 1 ? ms : cs;
+        for (int v = 0; v < kFinVariants && e == hipSuccess; ++v) {
+            if (plan->n_items[g][v] == 0) continue;
+            FinArgs fa{};
+            fa.items = plan->d_items[g][v];
+            fa.insts = plan->d_insts;
+            fa.n_items = plan->n_items[g][v];
+            fa.use_inline = 0;
+            e = launch_rec_finalize(fa, plan->n_items[g][v], plan->lds_fin[v], v, fs);
+        }
+    }
+    if (branch && e == hipSuccess) {
+        e = hipEventRecord(plan->ev_join, ms);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, plan->ev_join, 0);
     }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
