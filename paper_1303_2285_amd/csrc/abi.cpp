@@ -577,12 +577,12 @@ AdjGeom adj_geometry(int N, int M, int P, int Q)
     AdjGeom g{};
     const int Kr = N - P + 1, Kc = M - Q + 1;
     g.n_lags = (2 * P - 1) * (2 * Q - 1);
-    g.ndc = ((2 * Q - 1 + 15) / 16) * 16;
+    g.ndc = ((2 * Q - 1 + kAdjRing - 1) / kAdjRing) * kAdjRing;
     g.lds_tables = (size_t)(P + 1) * (Q + 1) * 16;
     const int rows = kAdjTR + 2 * (P - 1);
     const int stride = (kAdjTC + g.ndc) | 1;
     g.lds_interior = std::max((size_t)(2 * P - 1) * g.ndc * 16 + (size_t)rows * stride * 8,
-                              (size_t)256 * 16 * 16);
+                              (size_t)256 * kAdjRing * 16);
     const bool interior = Kr > P - 1 && Kc > Q - 1 && g.lds_interior <= 150 * 1024;
     if (interior) {
         g.ir0 = P - 1;

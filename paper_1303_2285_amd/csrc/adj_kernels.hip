@@ -23,6 +23,8 @@
 //                border column get their own weights (corner jobs).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "adj_internal.hpp"
 
 namespace covest {
@@ -166,9 +168,8 @@ __device__ __forceinline__ double2 block_sum_256(double2 v, double2 *red)
 //   column job: x = dc+Q-1, y = dr+P-1, T[x][j] = A[r0-(P-1)+j][c+dc]
 // staged in LDS in slabs of x; wave w takes x = w, w+4, ... of each slab and
 // the four waves' sums are added in wave order.
-__global__ void __launch_bounds__(256) adj_frame(AdjArgs aa)
+__device__ void adj_frame_job(const AdjArgs &aa, double2 *sm, int64_t job)
 {
-    extern __shared__ double2 sm[];
     const int P = aa.P, Q = aa.Q, N = aa.N, M = aa.M;
     const int tid = threadIdx.x;
     const int nbc = M - (aa.ic1 - aa.ic0);
@@ -176,7 +177,6 @@ __global__ void __launch_bounds__(256) adj_frame(AdjArgs aa)
     const int nlr = (aa.ir1 - aa.ir0 + kAdjFL - 1) / kAdjFL;
     const int64_t nrow_jobs = (int64_t)(N - (aa.ir1 - aa.ir0)) * nlc;
     const int64_t ncol_jobs = (int64_t)nbc * nlr;
-    const int64_t job = blockIdx.x;
     auto band_row = [&](int k) { return k < aa.ir0 ? k : aa.ir1 + (k - aa.ir0); };
     auto band_col = [&](int k) { return k < aa.ic0 ? k : aa.ic1 + (k - aa.ic0); };
 
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) adj_frame(AdjArgs aa)
     const int X = rowjob ? 2 * P - 1 : 2 * Q - 1, Y = rowjob ? 2 * Q - 1 : 2 * P - 1;
     const int span = kAdjFL + Y - 1;
     const int stride = span | 1;
-    const int XS = max(1, min(X, kAdjFrameLds / (Y * 16 + stride * 8)));
+    const int XS = max(1, min(X, aa.frame_lds / (Y * 16 + stride * 8)));
     double2 *Wt = sm;                                               // XS x Y
     float2 *Tt = reinterpret_cast<float2 *>(sm + (size_t)XS * Y);   // XS x stride
     const int u = tid % 64, wv = tid / 64;
@@ -279,17 +279,16 @@ __global__ void __launch_bounds__(256) adj_frame(AdjArgs aa)
 }
 
 // D2, interior: workgroup tile of kAdjTR rows x kAdjTC columns of outputs.
-// Thread (row, 16-column chunk, dr group): ring over dc, 16 FP64 accumulators;
-// the dr groups are summed through LDS in a fixed order.
-__global__ void __launch_bounds__(256) adj_interior(AdjArgs aa)
+// Thread (row, kAdjRing-column chunk, dr group): ring over dc, kAdjRing FP64
+// accumulators; the dr groups are summed through LDS in a fixed order.
+__device__ void adj_interior_tile(const AdjArgs &aa, double2 *sm, int tile)
 {
-    extern __shared__ double2 sm[];
     const int P = aa.P, Q = aa.Q;
     const int ndc = aa.ndc;                        // dc steps padded to a multiple of 16
     const int nlag_c = 2 * Q - 1;
     const int tiles_c = (aa.ic1 - aa.ic0 + kAdjTC - 1) / kAdjTC;
-    const int r0 = aa.ir0 + (blockIdx.x / tiles_c) * kAdjTR;
-    const int c0 = aa.ic0 + (blockIdx.x % tiles_c) * kAdjTC;
+    const int r0 = aa.ir0 + (tile / tiles_c) * kAdjTR;
+    const int c0 = aa.ic0 + (tile % tiles_c) * kAdjTC;
     const int rows = kAdjTR + 2 * (P - 1);
     const int cols = kAdjTC + ndc;                 // columns c0-(Q-1) .. c0+TC+ndc-(Q-1)
     const int stride = cols | 1;
@@ -310,31 +309,32 @@ __global__ void __launch_bounds__(256) adj_interior(AdjArgs aa)
     __syncthreads();
 
     const int lr = threadIdx.x % kAdjTR;
-    const int ch = (threadIdx.x / kAdjTR) % (kAdjTC / 16);
-    const int grp = threadIdx.x / (kAdjTR * (kAdjTC / 16));
-    constexpr int ngrp = 256 / (kAdjTR * (kAdjTC / 16));
+    constexpr int RG = kAdjRing;
+    const int ch = (threadIdx.x / kAdjTR) % (kAdjTC / RG);
+    const int grp = threadIdx.x / (kAdjTR * (kAdjTC / RG));
+    constexpr int ngrp = 256 / (kAdjTR * (kAdjTC / RG));
     const int ndr = 2 * P - 1;
     const int dr0 = (int)((int64_t)grp * ndr / ngrp), dr1 = (int)((int64_t)(grp + 1) * ndr / ngrp);
 
-    double2 acc[16];
+    double2 acc[RG];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = dz();
+    for (int u = 0; u < RG; ++u) acc[u] = dz();
     for (int di = dr0; di < dr1; ++di) {           // di = dr + P - 1
-        // output (lr, 16*ch + u) reads A[lr + di][16*ch + u + dj] (tile coordinates)
-        const float2 *arow = At + (lr + di) * stride + 16 * ch;
+        // output (lr, RG*ch + u) reads A[lr + di][RG*ch + u + dj] (tile coordinates)
+        const float2 *arow = At + (lr + di) * stride + RG * ch;
         const double2 *wrow = Wt + di * ndc;
-        double2 ring[16];
+        double2 ring[RG];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) ring[k] = make_double2(arow[k].x, arow[k].y);
-        for (int b = 0; b < ndc; b += 16) {
+        for (int k = 0; k < RG - 1; ++k) ring[k] = make_double2(arow[k].x, arow[k].y);
+        for (int b = 0; b < ndc; b += RG) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
+            for (int v = 0; v < RG; ++v) {
                 // dj = b + v; outputs u need arow[u + dj]
-                const float2 an = arow[b + v + 15];
-                ring[(v + 15) % 16] = make_double2(an.x, an.y);
+                const float2 an = arow[b + v + RG - 1];
+                ring[(v + RG - 1) % RG] = make_double2(an.x, an.y);
                 const double2 wv = wrow[b + v];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) cmla(acc[u], ring[(v + u) % 16], wv);
+                for (int u = 0; u < RG; ++u) cmla(acc[u], ring[(v + u) % RG], wv);
             }
         }
     }
@@ -342,17 +342,17 @@ __global__ void __launch_bounds__(256) adj_interior(AdjArgs aa)
     // fixed-order sum over the dr groups
     double2 *red = sm;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) red[threadIdx.x * 16 + u] = acc[u];
+    for (int u = 0; u < RG; ++u) red[threadIdx.x * RG + u] = acc[u];
     __syncthreads();
-    constexpr int per_grp = kAdjTR * (kAdjTC / 16);
+    constexpr int per_grp = kAdjTR * (kAdjTC / RG);
     for (int e = threadIdx.x; e < kAdjTR * kAdjTC; e += 256) {
         const int row = e / kAdjTC, col = e - row * kAdjTC;
         const int r = r0 + row, c = c0 + col;
         if (r >= aa.ir1 || c >= aa.ic1) continue;
-        const int tid0 = row + kAdjTR * (col / 16);
+        const int tid0 = row + kAdjTR * (col / RG);
         double2 s = dz();
         for (int g = 0; g < ngrp; ++g) {
-            const double2 v = red[(tid0 + g * per_grp) * 16 + (col % 16)];
+            const double2 v = red[(tid0 + g * per_grp) * RG + (col % RG)];
             s.x += v.x;
             s.y += v.y;
         }
@@ -360,15 +360,34 @@ __global__ void __launch_bounds__(256) adj_interior(AdjArgs aa)
     }
 }
 
-hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int n_interior_blocks,
+// D2 in one launch: blocks [0, n_interior) take the interior tiles, the rest
+// the frame's jobs, so that the frame's many short jobs run beside the
+// interior's long ones instead of after them.
+__global__ void __launch_bounds__(256) adj_main(AdjArgs aa, int n_interior)
+{
+    extern __shared__ double2 sm[];
+    if ((int)blockIdx.x < n_interior) adj_interior_tile(aa, sm, blockIdx.x);
+    else adj_frame_job(aa, sm, (int64_t)blockIdx.x - n_interior);
+}
+
+hipError_t launch_adjoint(const AdjArgs &aa_in, int n_lags, size_t lds_tables, int n_interior_blocks,
                           size_t lds_interior, int64_t n_frame_jobs, hipStream_t s)
 {
+    // One launch holds both kinds of blocks, so they share its LDS size: the
+    // interior's when there are interior tiles (the frame's slabs adapt to it;
+    // one slab of weights and A columns and the final 256-entry sum must fit),
+    // else the frame's own.
+    AdjArgs aa = aa_in;
+    const int P = aa.P, Q = aa.Q;
+    const int slab_max = std::max((2 * Q - 1) * 16 + ((kAdjFL + 2 * P - 2) | 1) * 8,
+                                  (2 * P - 1) * 16 + ((kAdjFL + 2 * Q - 2) | 1) * 8);
+    const size_t frame_min = std::max<size_t>(256 * 16, slab_max);
+    size_t lds = n_interior_blocks > 0 ? lds_interior : 0;
+    if (n_frame_jobs > 0) lds = n_interior_blocks > 0 ? std::max(lds, frame_min) : (size_t)kAdjFrameLds;
+    aa.frame_lds = (int)lds;
     static bool attr = false;
     if (!attr) {
-        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_frame),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, kAdjFrameLds);
-        if (e0 != hipSuccess) return e0;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_interior),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_main),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_tables),
@@ -379,13 +398,9 @@ hipError_t launch_adjoint(const AdjArgs &aa, int n_lags, size_t lds_tables, int 
     hipLaunchKernelGGL(adj_tables, dim3(n_lags), dim3(256), lds_tables, s, aa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (n_interior_blocks > 0) {
-        hipLaunchKernelGGL(adj_interior, dim3(n_interior_blocks), dim3(256), lds_interior, s, aa);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (n_frame_jobs > 0) {
-        hipLaunchKernelGGL(adj_frame, dim3((unsigned)n_frame_jobs), dim3(256), kAdjFrameLds, s, aa);
+    const int64_t n = n_interior_blocks + n_frame_jobs;
+    if (n > 0) {
+        hipLaunchKernelGGL(adj_main, dim3((unsigned)n), dim3(256), lds, s, aa, n_interior_blocks);
         e = hipGetLastError();
     }
     return e;
