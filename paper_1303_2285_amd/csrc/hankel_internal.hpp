@@ -24,8 +24,15 @@ struct HItem {
 
 // 16-bit forms: an item's FP32 accumulators sum at most this many positions
 // (each matrix-core step rounds once per 8 positions); the split-K reduction
-// adds the items' partial tiles in FP64.
+// adds the items' partial tiles in FP64.  The plain BF16 / FP16 forms, whose
+// error is that of their 16-bit inputs, take twice as many; small-integer
+// inputs stay exact either way (|sum| < 2^24).
 constexpr int kItemPositions16 = 16384;
+constexpr int kItemPositionsPlain16 = 32768;
+inline int item_positions16(int prec)
+{
+    return prec == kPrecBF16 || prec == kPrecF16 ? kItemPositionsPlain16 : kItemPositions16;
+}
 
 // One output tile and the range of items whose partial tiles it sums.
 struct HTile {

@@ -28,7 +28,7 @@
 // once into packed 16-bit planes (B1), so staging is a plain copy; a wave owns
 // a 64 x 64 block (64 x 32 for FP16x3) and every operand it reads feeds four
 // (two) matrix instructions; the FP32 accumulators sum one item of at most
-// kItemPositions16 positions, and the reduction adds the items' FP32 partial
+// item_positions16(prec) positions, and the reduction adds the items' FP32 partial
 // tiles in FP64 in a fixed order (B3).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>

@@ -508,7 +508,7 @@ static int bank_stride(int w, int P, int PQ, int k_lo_step, int rows)
 
 // 16-bit forms (B1-B3): A is split once into packed planes, workgroups own
 // 128 x 128 tiles (128 x 64 for FP16x3, whose cross terms keep accumulators of
-// their own), each item sums at most kItemPositions16 positions in FP32.
+// their own), each item sums at most item_positions16(prec) positions in FP32.
 static HankelPlan make_hankel_plan16(int N, int M, int P, int Q, int prec, int n_cu)
 {
     HankelPlan hp;
@@ -532,16 +532,17 @@ static HankelPlan make_hankel_plan16(int N, int M, int P, int Q, int prec, int n
     };
     const int span_a = span_of(hp.tm), span_b = span_of(hp.tn);
     // item geometry: rows of positions x a column range, at most
-    // kItemPositions16 positions, and at least ~4 items per workgroup slot
+    // item_positions16(prec) positions, and at least ~4 items per workgroup slot
     int rows_item, cols_item;
-    if (Kc <= kItemPositions16) {
+    const int item_pos = item_positions16(prec);
+    if (Kc <= item_pos) {
         // Items of equal rows, one workgroup each, two resident per CU.  The
         // split count S (items per tile) minimises rounds of workgroups times
         // the rows of one item plus a halo allowance (the P - 1 extra rows every
         // staged sub-block reads, worth ~4 rows of compute), so that the last
         // round is not left half empty.
         cols_item = Kc;
-        const int rows_max = std::max(1, std::min(Kr, kItemPositions16 / Kc));
+        const int rows_max = std::max(1, std::min(Kr, item_pos / Kc));
         const int64_t slots = 2LL * std::max(1, n_cu);
         const int64_t nt = (int64_t)tiles.size();
         const int s_lo = (Kr + rows_max - 1) / rows_max;
@@ -559,7 +560,7 @@ static HankelPlan make_hankel_plan16(int N, int M, int P, int Q, int prec, int n
         }
     } else {
         rows_item = 1;
-        cols_item = kItemPositions16;
+        cols_item = item_pos;
     }
     // sub-tile: the most positions per staged word within the LDS budget
     const size_t budget = 76 * 1024;

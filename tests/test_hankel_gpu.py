@@ -134,9 +134,9 @@ def test_fill_upper(cv, torch_dev, oracle_mod, prec):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3", "fp16", "fp16x3"])
 def test_long_rows_integer_exact(cv, torch_dev, oracle_mod, prec):
-    """Rows of more positions than one item sums (16384): items split along
-    the row; integer input, exact."""
-    A = synth.small_int(6, 17000, seed=31)
+    """Rows of more positions than one item sums (16384 for the split forms,
+    32768 for the plain ones): items split along the row; integer input, exact."""
+    A = synth.small_int(6, 33000, seed=31)
     P, Q = 3, 5
     _note("hankel long rows", prec)
     C = hankel(cv, torch_dev, A, P, Q, prec, normalize=False)

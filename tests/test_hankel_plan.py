@@ -75,7 +75,8 @@ def model(A, P, Q, prec, n_cu, check_only=False):
             it = items[i]
             assert it[0] == t[0] and it[1] == t[1]
             assert 0 <= it[2] < it[3] <= Kr and 0 <= it[4] < it[5] <= Kc
-            assert (it[3] - it[2]) * (it[5] - it[4]) <= 16384 or (it[3] - it[2]) == 1
+            limit = 32768 if prec in ("bf16", "fp16") else 16384
+            assert (it[3] - it[2]) * (it[5] - it[4]) <= limit or (it[3] - it[2]) == 1
             cover[it[2]:it[3], it[4]:it[5]] += 1
         assert np.all(cover == 1)
     partial = {}
@@ -183,7 +184,8 @@ def test_model_many_items(oracle_mod, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("shape", [(1024, 1024, 32, 32), (256, 256, 16, 16), (512, 512, 64, 64),
-                                   (600, 700, 64, 3), (40, 20000, 4, 64), (33, 17000, 32, 5)],
+                                   (600, 700, 64, 3), (40, 20000, 4, 64), (33, 17000, 32, 5),
+                                   (20, 40000, 3, 7)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_address_bounds_large(shape, prec):
     """Every item of the large plans (the headline size among them, and rows
