@@ -200,3 +200,27 @@ def test_sar_grid_full_size_integer_bit_exact(cv, torch_dev, oracle_mod):
     for a, b in picks:
         ref = oracle_mod.forward(aperture(img, a, b, (ar, ac), (sr, sc)), P, Q, threads=oracle_mod.max_threads())
         assert np.array_equal(R[a, b], ref), (a, b)
+
+
+def test_dense_grid_step16(cv, torch_dev, oracle_mod):
+    """A dense grid, as for the hundreds of thousands of apertures of a large
+    image (Sec. 2.3): 100 x 100 apertures at a step of 16 over a 420 x 420
+    integer image (21 x 21 = 441 apertures, each row of pixels in up to 7 of
+    them), 10 x 10 window.  Sampled apertures bit-exact against the oracle, the
+    trace identity on all of them."""
+    img = synth.small_int(420, 420, seed=79)
+    ap, step, n, P, Q = (100, 100), (16, 16), (21, 21), 10, 10
+    _note("aperture grid 420x420 ap 100 step 16 (dense)")
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q)
+    assert R.shape == (21, 21, P * Q, P * Q)
+    rng = np.random.default_rng(80)
+    picks = {(0, 0), (20, 20), (0, 20), (20, 0), (10, 10)} | {tuple(x) for x in rng.integers(0, 21, (6, 2))}
+    for (a, b) in sorted(picks):
+        ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q, threads=oracle_mod.max_threads())
+        got = R[a, b]
+        assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag), (a, b)
+    for a in range(n[0]):
+        for b in range(n[1]):
+            tr = np.trace(R[a, b]).real
+            want = trace_identity(aperture(img, a, b, ap, step), P, Q)
+            assert abs(tr - want) <= 1e-12 * want, (a, b)
