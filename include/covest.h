@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define COVEST_VERSION 4
+#define COVEST_VERSION 5
 
 typedef enum {
     COVEST_OK = 0,
@@ -89,10 +89,21 @@ typedef enum {
                                   of 7-8 tiles under 30% real (P = 56..64, Q = 4); in a
                                   batch only windows whose tiles are at least 70% real */
     COVEST_ENGINE_VECTOR = 1,  /* FP64 FMA on the vector units, lags in a register ring  */
-    COVEST_ENGINE_MATRIX = 2   /* FP64 MFMA: per line, a block of A times a Toeplitz band
+    COVEST_ENGINE_MATRIX = 2,  /* FP64 MFMA: per line, a block of A times a Toeplitz band
                                   of the line; needs N >= 2P-1, M >= 2Q-1, Q >= 4 and a
                                   lag block of at most 8 tiles of 16 x 16
                                   (COVEST_ERR_UNSUPPORTED otherwise)                     */
+    COVEST_ENGINE_LANE = 3     /* one lane per unique combination (Sec. 3.1) of one input:
+                                  the lane slides its box sums down and across the input
+                                  (the shift rule of Sec. 3.3 in both directions) and
+                                  writes every entry itself -- no finalize, no workspace.
+                                  For many small inputs (aperture plans pick it under
+                                  AUTO); one input is one workgroup, slow on its own.
+                                  Needs Q <= 16, PQ + (P-1)(Q-1) <= 512 and
+                                  (P+3)g + 8M <= 4096, g = M+2Q-2 rounded up to odd
+                                  (its staged rows fit 64 KB of LDS); FP64 or
+                                  FP32 output; covest_forward, _ex, _noalloc and aperture
+                                  plans only (COVEST_ERR_UNSUPPORTED otherwise)          */
 } covest_engine;
 
 typedef struct {
@@ -252,7 +263,17 @@ int covest_plan_batched_create_ex(covest_plan **out, const covest_problem_ex *pr
  * ((n_rows-1)*row_step + ap_rows > H, likewise for columns), for a window
  * larger than an aperture, or for more than 2^31 - 1 apertures; otherwise as
  * covest_plan_batched_create.  The image and R must stay valid while the
- * plan is used; covest_forward_batched recomputes every R from the image. */
+ * plan is used; covest_forward_batched recomputes every R from the image.
+ * Engines: COVEST_ENGINE_LANE (one launch, no workspace) is what AUTO picks
+ * when the window fits it and the grid has at least as many apertures as the
+ * device has compute units; VECTOR and MATRIX build the batched plan of
+ * strided views.  The lane engine shares work between overlapping apertures
+ * of a grid column: when the row step is below half the box height plus P-1,
+ * one workgroup walks several apertures down the image (its box slides from
+ * one aperture's last window row to the next aperture's first, instead of
+ * summing a new box), as many as keep four workgroups per compute unit;
+ * COVEST_AP_CHAIN=n in the environment at plan creation fixes that count
+ * (n >= 1; results change only by rounding). */
 typedef struct {
     const void *image;
     int64_t ld, H, W;

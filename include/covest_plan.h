@@ -121,6 +121,21 @@ int covest_hankel_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t p
 int covest_engine_choice(int64_t N, int64_t M, int64_t P, int64_t Q, int32_t batch, int32_t *engine,
                          int32_t *fits);
 
+/* Plan of the lane engine (COVEST_ENGINE_LANE) for a grid of n_rows x n_cols
+ * inputs of N x M at row step row_step (a single input: 1 x 1) on n_cu
+ * compute units: whether the engine fits the shape, the register array of
+ * column offsets (qmax), the second-factor ring rows and LDS row stride
+ * (complex64 elements), the row steps per staged chunk, the dynamic LDS
+ * bytes, the inputs per workgroup along a grid column (chain; the
+ * environment's COVEST_AP_CHAIN is not applied here), the workgroups and the
+ * threads per workgroup.  COVEST_ERR_SHAPE on a bad shape or grid. */
+typedef struct {
+    int32_t fits, qmax, ring, gstride, chunk, chain, n_blocks, threads;
+    int64_t lds;
+} covest_lane_plan_info;
+int covest_lane_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int64_t row_step, int64_t n_rows,
+                         int64_t n_cols, int32_t n_cu, covest_lane_plan_info *out);
+
 #ifdef __cplusplus
 }
 #endif

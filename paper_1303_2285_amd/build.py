@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcovest.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["rec_kernels.hip", "rec_mfma.hip", "hankel_kernels.hip", "adj_kernels.hip", "capon_kernels.hip", "noalloc.hip"]
+HIP_SOURCES = ["rec_kernels.hip", "rec_mfma.hip", "hankel_kernels.hip", "adj_kernels.hip", "capon_kernels.hip", "noalloc.hip",
+               "lane_kernels.hip"]
 CPP_SOURCES = ["plan.cpp", "abi.cpp"]
 
 

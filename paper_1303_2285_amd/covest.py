@@ -30,7 +30,7 @@ ERR_PLAN_MISMATCH = -6
 FORMS = {"auto": 0, "recurrence": 1, "hankel": 2, "hankel_mfma": 2}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3, "bf16": 4, "fp16": 5}
 FILLS = {"full": 0, "upper": 1}
-ENGINES = {"auto": 0, "vector": 1, "matrix": 2}
+ENGINES = {"auto": 0, "vector": 1, "matrix": 2, "lane": 3}
 
 
 class CovestError(RuntimeError):
@@ -87,6 +87,11 @@ class covest_mfma_plan_info(ctypes.Structure):
                                               "fin_products")]
 
 
+class covest_lane_plan_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("fits", "qmax", "ring", "gstride", "chunk", "chain", "n_blocks",
+                                               "threads")] + [("lds", ctypes.c_int64)]
+
+
 class covest_hankel_plan_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("pb", "qb", "stride_a", "stride_b", "tm", "tn", "npl", "ldp",
                                                "n_items", "n_tiles", "n_index")] + \
@@ -141,6 +146,8 @@ SIGNATURES = {
                                       ctypes.POINTER(covest_hankel_plan_info), _vp, _vp, _vp]),
     "covest_engine_choice": (_int, [_i64, _i64, _i64, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]),
+    "covest_lane_plan_get": (_int, [_i64, _i64, _i64, _i64, _i64, _i64, _i64, ctypes.c_int32,
+                                    ctypes.POINTER(covest_lane_plan_info)]),
 }
 
 _lib = None
@@ -576,6 +583,13 @@ def covest_forward_stamped(A, P: int, Q: int, *, engine="auto"):
         ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), nbytes, ctypes.c_void_p(stamps.data_ptr()),
         2 * n_uc, items.ctypes.data, _stream_handle(A.device)))
     return R, stamps, items
+
+
+def lane_plan(N, M, P, Q, row_step=1, n_rows=1, n_cols=1, n_cu=256):
+    """Plan of the lane engine for a grid of inputs (covest_lane_plan_get, host only) as a dict."""
+    info = covest_lane_plan_info()
+    _check(lib().covest_lane_plan_get(N, M, P, Q, row_step, n_rows, n_cols, n_cu, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in covest_lane_plan_info._fields_}
 
 
 def hankel_plan(N, M, P, Q, precision, n_cu=256):

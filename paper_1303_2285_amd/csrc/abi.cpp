@@ -23,6 +23,7 @@
 #include "covest_plan.h"
 #include "adj_internal.hpp"
 #include "capon_internal.hpp"
+#include "lane_internal.hpp"
 #include "launch.hpp"
 #include "noalloc_internal.hpp"
 #include "plan.hpp"
@@ -123,7 +124,7 @@ int check_opts(const covest_opts &o)
     for (int w : {o.ring_cols, o.ring_rows})
         if (w != 0 && w != 4 && w != 8 && w != 12 && w != 16)
             return fail(COVEST_ERR_INVALID_ARG, "ring widths are 0, 4, 8, 12 or 16 (got %d)", w);
-    if (o.engine < COVEST_ENGINE_AUTO || o.engine > COVEST_ENGINE_MATRIX)
+    if (o.engine < COVEST_ENGINE_AUTO || o.engine > COVEST_ENGINE_LANE)
         return fail(COVEST_ERR_INVALID_ARG, "unknown engine %d", (int)o.engine);
     return COVEST_OK;
 }
@@ -282,6 +283,9 @@ int finish_call(hipStream_t stream)
 // when the requested engine cannot run the shape.
 int rec_engine(int N, int M, int P, int Q, int64_t lda, const covest_opts &o, int *engine)
 {
+    if (o.engine == COVEST_ENGINE_LANE)
+        return fail(COVEST_ERR_UNSUPPORTED, "the lane engine runs covest_forward, _ex, _noalloc and aperture "
+                                            "plans only");
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
     if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
@@ -439,6 +443,86 @@ int rec_forward_noalloc(const void *A, int64_t lda, int N, int M, int P, int Q, 
                       reinterpret_cast<const MJob *>(base + l.mjobs), 1};
     const Inst in = make_inst(*sp, A, lda, R, ldr, base + l.ws, o);
     return rec_launch(*sp, t, in, stream);
+}
+
+// ----------------------------------------------------------- lane engine ----
+int lane_check(int N, int M, int P, int Q, const covest_opts &o)
+{
+    if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
+        return fail(COVEST_ERR_UNSUPPORTED, "the lane engine computes in FP64 (prec FP64 or FP32 output)");
+    if (!lane_fits(N, M, P, Q))
+        return fail(COVEST_ERR_UNSUPPORTED,
+                    "the lane engine needs Q <= %d, PQ + (P-1)(Q-1) <= %d and %zu bytes of staged rows "
+                    "<= %zu (N=%d M=%d P=%d Q=%d)",
+                    kLaneMaxQ, kLaneMaxLags, lane_lds_bytes(M, P, Q), kLaneMaxLds, N, M, P, Q);
+    return COVEST_OK;
+}
+
+// Inputs per workgroup along a grid column.  A new box costs Kr + 2(P-1)
+// row walks (the first Kr rows, then two per window row); the next input of
+// a chain costs 2*row_step (its box slides down from the previous input's).
+// Chains are as long as keep four workgroups per compute unit.
+int lane_chain(int N, int P, int64_t row_step, int64_t n_rows, int64_t n_cols, int cus, bool env)
+{
+    if (env) {
+        if (const char *e = std::getenv("COVEST_AP_CHAIN")) {
+            const long v = std::strtol(e, nullptr, 10);
+            if (v >= 1) return (int)std::min<int64_t>(v, n_rows);
+        }
+    }
+    const int Kr = N - P + 1;
+    if (2 * row_step >= (int64_t)Kr + 2 * (P - 1)) return 1;
+    const int64_t target = 4 * (int64_t)cus;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n_rows, n_rows * n_cols / target));
+}
+
+LaneArgs make_lane_args(const void *image, int64_t ld, int N, int M, int P, int Q, int64_t row_step,
+                        int64_t col_step, int64_t n_rows, int64_t n_cols, int chain, void *R, int64_t ldr,
+                        int64_t r_stride, const covest_opts &o)
+{
+    LaneArgs la{};
+    la.image = static_cast<const float2 *>(image);
+    la.ld = ld;
+    la.N = N;
+    la.M = M;
+    la.P = P;
+    la.Q = Q;
+    la.Kr = N - P + 1;
+    la.Kc = M - Q + 1;
+    la.row_step = (int)row_step;
+    la.col_step = (int)col_step;
+    la.n_rows = (int)n_rows;
+    la.n_cols = (int)n_cols;
+    la.chain = chain;
+    la.n_lags = lane_n_lags(P, Q);
+    la.R = R;
+    la.ldr = ldr;
+    la.r_stride = r_stride;
+    la.out_fp64 = o.prec == COVEST_PREC_FP64 ? 1 : 0;
+    la.fill_full = o.fill == COVEST_FILL_FULL ? 1 : 0;
+    la.normalize = o.normalize ? 1 : 0;
+    la.gstride = lane_gstride(M, Q);
+    la.ring = lane_ring(P);
+    return la;
+}
+
+int lane_blocks(const LaneArgs &la) { return la.n_cols * ((la.n_rows + la.chain - 1) / la.chain); }
+
+int lane_run(const LaneArgs &la, hipStream_t stream)
+{
+    HIP_TRY(timed("lane_main", stream, [&] {
+        return launch_lane(la, lane_blocks(la), lane_lds_bytes(la.M, la.P, la.Q), stream);
+    }));
+    return finish_call(stream);
+}
+
+// One input on the lane engine: a 1 x 1 grid.
+int lane_forward(const void *A, int64_t lda, int N, int M, int P, int Q, void *R, int64_t ldr,
+                 const covest_opts &o, hipStream_t stream)
+{
+    int st = lane_check(N, M, P, Q, o);
+    if (st != COVEST_OK) return st;
+    return lane_run(make_lane_args(A, lda, N, M, P, Q, 1, 1, 1, 1, 1, R, ldr, 0, o), stream);
 }
 
 // ------------------------------------------------------------ plain form ----
@@ -634,6 +718,9 @@ struct covest_plan {
     };
     std::vector<MfmaLaunch> mfma;
     int n_matrix = 0;   // problems on the matrix-core engine
+    // aperture plans on the lane engine: one launch, no tables, no graph
+    bool lane = false;
+    LaneArgs lane_args{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double est_cost = 0.0;
@@ -1127,6 +1214,9 @@ int create_batched(covest_plan **out, const covest_problem_ex *problems, int64_t
     if (st != COVEST_OK) return st;
     if (o.form == COVEST_FORM_HANKEL_MFMA)
         return fail(COVEST_ERR_UNSUPPORTED, "batched plans use the recurrence form");
+    if (o.engine == COVEST_ENGINE_LANE)
+        return fail(COVEST_ERR_UNSUPPORTED, "batched plans run on the vector or matrix engines; aperture plans "
+                                            "take the lane engine");
     if (o.prec != COVEST_PREC_FP64 && o.prec != COVEST_PREC_FP32)
         return fail(COVEST_ERR_UNSUPPORTED, "batched plans compute in FP64 (prec FP64 or FP32 output)");
     for (int64_t i = 0; i < count; ++i) {
@@ -1186,6 +1276,12 @@ int covest_workspace_size(int64_t N, int64_t M, int64_t P, int64_t Q, const cove
     st = check_shape(N, M, P, Q);
     if (st != COVEST_OK) return st;
     if (use_recurrence(o)) {
+        if (o.engine == COVEST_ENGINE_LANE) {
+            st = lane_check((int)N, (int)M, (int)P, (int)Q, o);
+            if (st != COVEST_OK) return st;
+            *bytes = 0;
+            return ok();
+        }
         if (P > kMaxWindow || Q > kMaxWindow)
             return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
         const int engine = pick_engine((int)N, (int)M, (int)P, (int)Q, o);
@@ -1218,6 +1314,8 @@ int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t 
     if (!A || !R) return fail(COVEST_ERR_INVALID_ARG, "A and R must be non-null device pointers");
     if (lda < M) return fail(COVEST_ERR_INVALID_ARG, "lda (%lld) < M (%lld)", (long long)lda, (long long)M);
     if (ldr < P * Q) return fail(COVEST_ERR_INVALID_ARG, "ldr (%lld) < PQ (%lld)", (long long)ldr, (long long)(P * Q));
+    if (use_recurrence(o) && o.engine == COVEST_ENGINE_LANE)
+        return lane_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, stream);
     if (use_recurrence(o))
         return rec_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, ws, ws_bytes, stream);
     return hankel_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, ws, ws_bytes, stream);
@@ -1242,6 +1340,8 @@ int covest_forward_noalloc(const void *A, int64_t lda, int64_t N, int64_t M, int
     if (ldr < P * Q) return fail(COVEST_ERR_INVALID_ARG, "ldr (%lld) < PQ (%lld)", (long long)ldr, (long long)(P * Q));
     if (!use_recurrence(o))
         return fail(COVEST_ERR_UNSUPPORTED, "the no-allocation entry point runs the recurrence form only");
+    if (o.engine == COVEST_ENGINE_LANE)   // allocates nothing and uses no scratch
+        return lane_forward(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, stream);
     return rec_forward_noalloc(A, lda, (int)N, (int)M, (int)P, (int)Q, R, ldr, o, stream);
 }
 
@@ -1373,8 +1473,39 @@ int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *
     if (P > kMaxWindow || Q > kMaxWindow)
         return fail(COVEST_ERR_UNSUPPORTED, "the recurrence form supports P, Q <= %d", kMaxWindow);
     const covest_opts o = resolve_opts(opts);
+    st = check_opts(o);
+    if (st != COVEST_OK) return st;
     const size_t esz = o.prec == COVEST_PREC_FP64 ? 16 : 8;
     const int64_t pq = P * Q, count = g.n_rows * g.n_cols;
+    if (use_recurrence(o) && o.engine == COVEST_ENGINE_LANE) {
+        st = lane_check((int)g.ap_rows, (int)g.ap_cols, (int)P, (int)Q, o);
+        if (st != COVEST_OK) return st;
+    }
+    const bool lane_ok = use_recurrence(o) && (o.prec == COVEST_PREC_FP64 || o.prec == COVEST_PREC_FP32) &&
+                         lane_fits((int)g.ap_rows, (int)g.ap_cols, (int)P, (int)Q);
+    if (lane_ok && (o.engine == COVEST_ENGINE_LANE || o.engine == COVEST_ENGINE_AUTO)) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        const int cus = cus_of_device(dev);
+        const bool lane = o.engine == COVEST_ENGINE_LANE || (count >= cus && o.ring_cols == 0 && o.ring_rows == 0);
+        if (lane) {
+            const int chain = lane_chain((int)g.ap_rows, (int)P, g.row_step, g.n_rows, g.n_cols, cus, true);
+            covest_plan *plan = new covest_plan();
+            plan->device = dev;
+            plan->opts = o;
+            plan->count = count;
+            plan->lane = true;
+            plan->lane_args = make_lane_args(g.image, g.ld, (int)g.ap_rows, (int)g.ap_cols, (int)P, (int)Q,
+                                             g.row_step, g.col_step, g.n_rows, g.n_cols, chain, R, pq, pq * pq, o);
+            const hipError_t e = prepare_lane_kernels();
+            if (e != hipSuccess) {
+                delete plan;
+                return fail(COVEST_ERR_HIP, "lane kernels: %s", hipGetErrorString(e));
+            }
+            *out = plan;
+            return ok();
+        }
+    }
     std::vector<covest_problem_ex> ex((size_t)count);
     for (int64_t a = 0; a < g.n_rows; ++a)
         for (int64_t b = 0; b < g.n_cols; ++b) {
@@ -1430,11 +1561,12 @@ int covest_capon_spectrum(const void *R, int64_t count, int64_t P, int64_t Q, in
 
 int covest_forward_batched(covest_plan *plan, hipStream_t stream)
 {
-    if (!plan || !plan->exec) return fail(COVEST_ERR_INVALID_ARG, "invalid plan");
+    if (!plan || (!plan->exec && !plan->lane)) return fail(COVEST_ERR_INVALID_ARG, "invalid plan");
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != plan->device)
         return fail(COVEST_ERR_PLAN_MISMATCH, "plan was built on device %d, current device is %d", plan->device, dev);
+    if (plan->lane) return lane_run(plan->lane_args, stream);
     HIP_TRY(timed("batched_graph", stream, [&] { return hipGraphLaunch(plan->exec, stream); }));
     return finish_call(stream);
 }
@@ -1633,6 +1765,27 @@ extern "C" int covest_hankel_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q
             std::memcpy(tiles + 4 * t, row, sizeof(row));
         }
     if (item_index) std::memcpy(item_index, hp.item_index.data(), hp.item_index.size() * sizeof(int32_t));
+    return ok();
+}
+
+extern "C" int covest_lane_plan_get(int64_t N, int64_t M, int64_t P, int64_t Q, int64_t row_step, int64_t n_rows,
+                                    int64_t n_cols, int32_t n_cu, covest_lane_plan_info *out)
+{
+    if (!out) return fail(COVEST_ERR_INVALID_ARG, "out is null");
+    int st = check_shape(N, M, P, Q);
+    if (st != COVEST_OK) return st;
+    if (row_step < 1 || n_rows < 1 || n_cols < 1 || n_rows > INT32_MAX / n_cols)
+        return fail(COVEST_ERR_SHAPE, "need row_step, n_rows, n_cols >= 1 and fewer than 2^31 inputs");
+    std::memset(out, 0, sizeof(*out));
+    out->fits = lane_fits((int)N, (int)M, (int)P, (int)Q) ? 1 : 0;
+    out->qmax = lane_qmax((int)Q);
+    out->ring = lane_ring((int)P);
+    out->gstride = lane_gstride((int)M, (int)Q);
+    out->chunk = kLaneChunk;
+    out->chain = lane_chain((int)N, (int)P, row_step, n_rows, n_cols, n_cu > 0 ? n_cu : 256, false);
+    out->n_blocks = (int32_t)(n_cols * ((n_rows + out->chain - 1) / out->chain));
+    out->threads = (lane_n_lags((int)P, (int)Q) + 63) / 64 * 64;
+    out->lds = (int64_t)lane_lds_bytes((int)M, (int)P, (int)Q);
     return ok();
 }
 

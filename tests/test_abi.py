@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert cv.version() == 4
+    assert cv.version() == 5
 
 
 def _opts(**kw):
@@ -58,9 +58,19 @@ def test_workspace_query_errors():
     bad = cv.make_opts(ring_cols=6)
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     bad = cv.make_opts()
-    bad.engine = 3
+    bad.engine = 4
     assert L.covest_workspace_size(64, 64, 8, 8, ctypes.byref(bad), ctypes.byref(n)) == cv.ERR_INVALID_ARG
     assert "engine" in L.covest_last_error().decode()
+    # the lane engine needs no workspace; it refuses windows beyond its
+    # register array (Q > 16), too many lags and rows too long for its LDS
+    n.value = 99
+    assert L.covest_workspace_size(100, 100, 10, 10, _opts(engine="lane"), ctypes.byref(n)) == cv.OK
+    assert n.value == 0
+    for shape in [(64, 64, 8, 17), (64, 64, 23, 16), (40, 1000, 10, 10)]:
+        assert L.covest_workspace_size(*shape, _opts(engine="lane"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED, shape
+        assert "lane engine" in L.covest_last_error().decode()
+    assert L.covest_workspace_size(64, 64, 8, 8, _opts(engine="lane", precision="bf16x3", form="recurrence"),
+                                   ctypes.byref(n)) == cv.ERR_UNSUPPORTED
     # the matrix-core engine: not where its kernel cannot run (Q < 4, N < 2P - 1);
     # its own plan where it can
     assert L.covest_workspace_size(64, 64, 8, 3, _opts(engine="matrix"), ctypes.byref(n)) == cv.ERR_UNSUPPORTED
@@ -157,6 +167,14 @@ def test_batched_and_aperture_argument_errors_before_device_use():
     assert "2^31" in L.covest_last_error().decode()
     assert create(grid(), P=80, Q=80) == cv.ERR_UNSUPPORTED
     assert create(grid(), opts=_opts(form="hankel", precision="fp32")) == cv.ERR_UNSUPPORTED
+    # the lane engine: windows it cannot hold, and no batched plans
+    assert create(grid(), P=10, Q=17, opts=_opts(engine="lane")) == cv.ERR_UNSUPPORTED
+    assert "lane engine" in L.covest_last_error().decode()
+    assert create(grid(), opts=_opts(engine="lane", precision="bf16x3")) == cv.ERR_UNSUPPORTED
+    arr[0].P = 8
+    assert L.covest_plan_batched_create_ex(ctypes.byref(plan), arr, 1, _opts(engine="lane"), None) \
+        == cv.ERR_UNSUPPORTED
+    assert "lane" in L.covest_last_error().decode()
     # the largest grid that fits: the last aperture ends exactly at the image edge
     assert create(grid(row_step=62, n_rows=25, H=24 * 62 + 100), opts=_opts(precision="fp16")) \
         == cv.ERR_UNSUPPORTED

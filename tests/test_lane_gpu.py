@@ -1,0 +1,190 @@
+"""GPU parity of the lane engine (one lane per unique combination of one
+input, box sums slid in registers, no finalize) against the CPU oracle
+(eq. 2.2): single inputs through covest_forward and aperture grids, with and
+without chains (several apertures of a grid column in one walk).
+
+Bar: bit-exact on small-integer inputs (every FP64 sum is an integer below
+2^53, one IEEE division per part); relative Frobenius error below 1e-12 on
+float inputs (exact FP64 products, another summation order); FP32 output
+within one rounding of the FP64 result.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1303_2285_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+
+def _note(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cv():
+    from paper_1303_2285_amd import covest
+    covest.lib()
+    return covest
+
+
+def relF(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def aperture(img, a, b, ap, step):
+    r0, c0 = a * step[0], b * step[1]
+    return np.ascontiguousarray(img[r0:r0 + ap[0], c0:c0 + ap[1]])
+
+
+def run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=None, **kw):
+    """R of every aperture on the lane engine; `chain` fixes the apertures per walk."""
+    torch, dev = torch_dev
+    old = os.environ.get("COVEST_AP_CHAIN")
+    if chain is not None:
+        os.environ["COVEST_AP_CHAIN"] = str(chain)
+    try:
+        plan = cv.AperturePlan(torch.from_numpy(img).to(dev), ap[0], ap[1], step[0], step[1], n[0], n[1], P, Q,
+                               engine=kw.pop("engine", "lane"), **kw)
+    finally:
+        if old is None:
+            os.environ.pop("COVEST_AP_CHAIN", None)
+        else:
+            os.environ["COVEST_AP_CHAIN"] = old
+    R = plan.run()
+    torch.cuda.synchronize()
+    out = R.cpu().numpy()
+    plan.close()
+    return out
+
+
+SINGLE = [(1, 1, 1, 1), (5, 7, 5, 7), (9, 4, 3, 4), (33, 17, 1, 16), (17, 33, 16, 1), (40, 33, 4, 16),
+          (64, 64, 8, 8), (100, 100, 10, 10), (70, 66, 16, 2), (12, 200, 3, 12), (150, 40, 7, 5)]
+
+
+@pytest.mark.parametrize("shape", SINGLE, ids=lambda s: "x".join(map(str, s)))
+def test_single_input_integer_bit_exact(cv, torch_dev, oracle_mod, shape):
+    torch, dev = torch_dev
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N * 13 + M + P + Q)
+    _note("lane single", shape)
+    R = cv.covest_forward(torch.from_numpy(A).to(dev), P, Q, engine="lane")
+    torch.cuda.synchronize()
+    assert np.array_equal(R.cpu().numpy(), oracle_mod.forward(A, P, Q))
+
+
+def test_single_input_options(cv, torch_dev, oracle_mod):
+    """Float input: FP64 to 1e-12, FP32 output within one rounding, the upper
+    fill leaves the lower triangle alone, normalize=0 gives the sums, and a
+    strided view of A and of R."""
+    torch, dev = torch_dev
+    A = synth.aperture_image(90, 120, seed=31)
+    P, Q, PQ = 9, 11, 99
+    At = torch.from_numpy(A).to(dev)
+    ref = oracle_mod.forward(A, P, Q)
+    _note("lane single options 90x120 9x11")
+    R = cv.covest_forward(At, P, Q, engine="lane").cpu().numpy()
+    assert relF(R, ref) <= TOL_FP64
+    assert np.array_equal(R, R.conj().T) and np.all(np.diag(R).imag == 0)
+    R32 = cv.covest_forward(At, P, Q, engine="lane", precision="fp32").cpu().numpy()
+    assert R32.dtype == np.complex64 and np.abs(R32 - ref).max() <= 2 ** -23 * np.abs(ref).max()
+    Ru = cv.covest_forward(At, P, Q, engine="lane", fill="upper").cpu().numpy()
+    iu, il = np.triu_indices(PQ), np.tril_indices(PQ, -1)
+    assert relF(Ru[iu], ref[iu]) <= TOL_FP64 and np.all(Ru[il] == 0)
+    C = cv.covest_forward(At, P, Q, engine="lane", normalize=False).cpu().numpy()
+    assert relF(C, oracle_mod.forward(A, P, Q, normalize=False)) <= TOL_FP64
+    big = torch.zeros((120, 200), dtype=torch.complex64, device=dev)
+    big[10:100, 30:150] = At
+    Rbig = torch.zeros((PQ, 128), dtype=torch.complex128, device=dev)
+    cv.covest_forward(big[10:100, 30:150], P, Q, engine="lane", out=Rbig[:, :PQ])
+    torch.cuda.synchronize()
+    assert relF(Rbig[:, :PQ].cpu().numpy(), ref) <= TOL_FP64
+    assert np.all(Rbig[:, PQ:].cpu().numpy() == 0)
+
+
+GRIDS = [
+    # image H x W, aperture, step, grid, P, Q, chain
+    ((90, 80), (30, 25), (12, 11), (6, 6), 5, 4, 1),
+    ((90, 80), (30, 25), (12, 11), (6, 6), 5, 4, 3),
+    ((90, 80), (30, 25), (12, 11), (6, 6), 5, 4, 6),
+    ((60, 60), (20, 20), (3, 4), (14, 11), 6, 6, 5),     # row step below P: shared box starts
+    ((60, 50), (12, 12), (1, 2), (49, 20), 3, 4, 49),    # step 1, one chain per grid column
+    ((160, 150), (64, 60), (32, 30), (4, 4), 16, 16, 4),
+    ((40, 36), (7, 6), (5, 5), (7, 7), 7, 6, 2),         # window = aperture (K = 1)
+    ((40, 36), (10, 10), (3, 2), (11, 14), 1, 1, 4),
+]
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: "_".join("x".join(map(str, x)) if isinstance(x, tuple)
+                                                          else str(x) for x in g))
+def test_grid_integer_bit_exact(cv, torch_dev, oracle_mod, g):
+    (H, W), ap, step, n, P, Q, chain = g
+    img = synth.small_int(H, W, seed=H + 3 * W + P + chain)
+    _note("lane grid", g)
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=chain)
+    assert R.shape == (n[0], n[1], P * Q, P * Q)
+    for a in range(n[0]):
+        for b in range(n[1]):
+            ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q)
+            assert np.array_equal(R[a, b], ref), (a, b)
+
+
+def test_grid_float_chains_fp32_upper(cv, torch_dev, oracle_mod):
+    """Float image, chained walks: FP64 to 1e-12, FP32 output, upper fill."""
+    img = synth.aperture_image(200, 170, seed=33)
+    ap, step, n, P, Q = (60, 50), (10, 12), (15, 10), 8, 7
+    _note("lane float grid chains")
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=15)
+    R32 = run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=4, precision="fp32")
+    Ru = run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=1, fill="upper")
+    iu, il = np.triu_indices(P * Q), np.tril_indices(P * Q, -1)
+    for a in range(n[0]):
+        for b in range(0, n[1], 3):
+            ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q)
+            assert relF(R[a, b], ref) <= TOL_FP64, (a, b)
+            assert np.abs(R32[a, b] - ref).max() <= 2 ** -23 * np.abs(ref).max(), (a, b)
+            assert relF(Ru[a, b][iu], ref[iu]) <= TOL_FP64 and np.all(Ru[a, b][il] == 0), (a, b)
+
+
+def test_sar_grid_lane_vs_batched(cv, torch_dev, oracle_mod):
+    """The imaging workload (1600 x 1600 image, 25 x 25 apertures of 100 x 100
+    at step 62, 10 x 10 window): AUTO (the lane engine here) against the
+    batched vector engine on all 625 apertures, and sampled apertures against
+    the oracle."""
+    H, W, ar, ac, sr, sc, nr, nc, P, Q, seed = synth.APERTURE_GRIDS["sar_1600"]
+    img = synth.aperture_image(H, W, seed)
+    _note("sar_1600 lane vs vector")
+    Rl = run_grid(cv, torch_dev, img, (ar, ac), (sr, sc), (nr, nc), P, Q, engine="auto")
+    Rv = run_grid(cv, torch_dev, img, (ar, ac), (sr, sc), (nr, nc), P, Q, engine="vector")
+    for a in range(nr):
+        for b in range(nc):
+            assert relF(Rl[a, b], Rv[a, b]) <= TOL_FP64, (a, b)
+    for a, b in [(0, 0), (nr - 1, nc - 1), (12, 7)]:
+        ref = oracle_mod.forward(aperture(img, a, b, (ar, ac), (sr, sc)), P, Q, threads=oracle_mod.max_threads())
+        assert relF(Rl[a, b], ref) <= TOL_FP64, (a, b)
+
+
+def test_dense_grid_chained(cv, torch_dev, oracle_mod):
+    """420 x 420 integer image, 21 x 21 apertures of 100 x 100 at step 16,
+    10 x 10 window, walked in chains of 7 apertures (the box slides 16 rows
+    from one aperture to the next): sampled apertures bit-exact, the last of
+    each chain among them."""
+    img = synth.small_int(420, 420, seed=81)
+    ap, step, n, P, Q = (100, 100), (16, 16), (21, 21), 10, 10
+    _note("dense grid chained 7")
+    R = run_grid(cv, torch_dev, img, ap, step, n, P, Q, chain=7)
+    for a, b in [(0, 0), (6, 3), (7, 3), (13, 20), (20, 20), (14, 0), (20, 9)]:
+        ref = oracle_mod.forward(aperture(img, a, b, ap, step), P, Q, threads=oracle_mod.max_threads())
+        assert np.array_equal(R[a, b], ref), (a, b)
