@@ -254,13 +254,7 @@ def _batched(covest, torch, dev, batch, reps):
     return out
 
 
-def _apertures(covest, synth, torch, dev, reps):
-    out = {}
-    H, W_img, ar, ac, sr, sc, nr, nc, Pa, Qa, seed = synth.APERTURE_GRIDS["sar_1600"]
-    img = torch.from_numpy(synth.aperture_image(H, W_img, seed)).to(dev)
-    t0 = time.perf_counter()
-    plan = covest.AperturePlan(img, ar, ac, sr, sc, nr, nc, Pa, Qa)
-    t_plan = time.perf_counter() - t0
+def _time_plan(plan, torch, reps):
     for _ in range(2):
         plan.run()
     torch.cuda.synchronize()
@@ -268,7 +262,39 @@ def _apertures(covest, synth, torch, dev, reps):
     for _ in range(reps):
         plan.run()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    return (time.perf_counter() - t0) / reps
+
+
+def _aperture_plan(covest, img, grid, engine="auto", chain=None):
+    """An aperture plan; `chain` fixes the lane engine's apertures per walk."""
+    ar, ac, sr, sc, nr, nc, P, Q = grid
+    old = os.environ.get("COVEST_AP_CHAIN")
+    if chain is not None:
+        os.environ["COVEST_AP_CHAIN"] = str(chain)
+    try:
+        return covest.AperturePlan(img, ar, ac, sr, sc, nr, nc, P, Q, engine=engine)
+    finally:
+        if chain is not None:
+            if old is None:
+                os.environ.pop("COVEST_AP_CHAIN", None)
+            else:
+                os.environ["COVEST_AP_CHAIN"] = old
+
+
+def _apertures(covest, synth, torch, dev, reps):
+    out = {}
+    H, W_img, ar, ac, sr, sc, nr, nc, Pa, Qa, seed = synth.APERTURE_GRIDS["sar_1600"]
+    img = torch.from_numpy(synth.aperture_image(H, W_img, seed)).to(dev)
+    grid = (ar, ac, sr, sc, nr, nc, Pa, Qa)
+    t0 = time.perf_counter()
+    plan = _aperture_plan(covest, img, grid)
+    t_plan = time.perf_counter() - t0
+    dt = _time_plan(plan, torch, reps)
+    # the same grid on the batched vector engine (strided views, one graph)
+    vplan = _aperture_plan(covest, img, grid, engine="vector")
+    dt_batched = _time_plan(vplan, torch, reps)
+    vplan.close()
+    del vplan
     n_ap = nr * nc
     um = n_ap * covest.counts(ar, ac, Pa, Qa)["um"]
     out["apertures"] = {"workload": f"{H}x{W_img} image of 8 2-D exponentials + noise (seed {seed}), "
@@ -277,8 +303,29 @@ def _apertures(covest, synth, torch, dev, reps):
                         "ms_per_image": dt * 1e3, "matrices_per_s": n_ap / dt,
                         "gflops_algorithmic": 8.0 * um / dt / 1e9,
                         "fp64_roof_ms": 8.0 * um / (FP64_PEAK_TFLOPS * 1e12) * 1e3,
-                        "r_write_gb_s": n_ap * (Pa * Qa) ** 2 * 16 / dt / 1e9, "plan_s": t_plan}
-    print(f"[bench] apertures: {dt * 1e3:.3f} ms per image ({n_ap} matrices)", file=sys.stderr, flush=True)
+                        "r_write_gb_s": n_ap * (Pa * Qa) ** 2 * 16 / dt / 1e9, "plan_s": t_plan,
+                        "engine": "lane (AUTO)", "ms_per_image_batched_vector_engine": dt_batched * 1e3}
+    print(f"[bench] apertures: {dt * 1e3:.3f} ms per image ({n_ap} matrices; batched vector engine "
+          f"{dt_batched * 1e3:.3f} ms)", file=sys.stderr, flush=True)
+    # a dense grid (step 16: 94 x 94 apertures of the same image): the lane
+    # engine walks several apertures of a grid column in one chain, sharing
+    # its slides between them, against one walk per aperture
+    dgrid = (ar, ac, 16, 16, (H - ar) // 16 + 1, (W_img - ac) // 16 + 1, Pa, Qa)
+    n_d = dgrid[4] * dgrid[5]
+    dplan = _aperture_plan(covest, img, dgrid)
+    t_chain = _time_plan(dplan, torch, 3)
+    chain = covest.lane_plan(ar, ac, Pa, Qa, 16, dgrid[4], dgrid[5])["chain"]
+    dplan.close()
+    del dplan
+    dplan = _aperture_plan(covest, img, dgrid, chain=1)
+    t_single = _time_plan(dplan, torch, 3)
+    dplan.close()
+    del dplan
+    out["apertures"]["dense_step16"] = {"apertures": n_d, "chain": chain, "ms_chained": t_chain * 1e3,
+                                        "ms_one_walk_per_aperture": t_single * 1e3,
+                                        "matrices_per_s": n_d / t_chain}
+    print(f"[bench] apertures, step 16 ({n_d}): {t_chain * 1e3:.3f} ms chained ({chain} per walk), "
+          f"{t_single * 1e3:.3f} ms one walk per aperture", file=sys.stderr, flush=True)
     # the consumer of R: the minimum-variance (Capon) spectrum of every aperture on a 64 x 64 grid
     F = 64
     R = plan.outputs

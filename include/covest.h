@@ -96,9 +96,10 @@ typedef enum {
     COVEST_ENGINE_LANE = 3     /* one lane per unique combination (Sec. 3.1) of one input:
                                   the lane slides its box sums down and across the input
                                   (the shift rule of Sec. 3.3 in both directions) and
-                                  writes every entry itself -- no finalize, no workspace.
-                                  For many small inputs (aperture plans pick it under
-                                  AUTO); one input is one workgroup, slow on its own.
+                                  writes every entry itself -- no finalize, no
+                                  workspace.  For many small inputs (aperture plans pick
+                                  it under AUTO); one input is one workgroup, slow on
+                                  its own.
                                   Needs Q <= 16, PQ + (P-1)(Q-1) <= 512 and
                                   (P+3)g + 8M <= 4096, g = M+2Q-2 rounded up to odd
                                   (its staged rows fit 64 KB of LDS); FP64 or
@@ -169,7 +170,7 @@ int covest_forward_ex(const void *A, int64_t lda, int64_t N, int64_t M, int64_t 
  * for covest_forward_ex; results are bitwise those of covest_forward_ex with
  * the same options.
  *   - form must be AUTO or RECURRENCE and prec FP64 or FP32 (the plain form:
- *     COVEST_ERR_UNSUPPORTED).
+ *     COVEST_ERR_UNSUPPORTED).  COVEST_ENGINE_LANE needs no scratch at all.
  *   - A shape whose tables plus workspace exceed the array is rejected with
  *     COVEST_ERR_WORKSPACE before any device work (covest_workspace_size()
  *     plus a few hundred KB of tables must fit; the 1024 x 1024 input with a

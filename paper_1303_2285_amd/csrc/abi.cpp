@@ -1499,7 +1499,7 @@ int covest_plan_apertures_create(covest_plan **out, const covest_aperture_grid *
                                              g.row_step, g.col_step, g.n_rows, g.n_cols, chain, R, pq, pq * pq, o);
             const hipError_t e = prepare_lane_kernels();
             if (e != hipSuccess) {
-                delete plan;
+                free_plan(plan);
                 return fail(COVEST_ERR_HIP, "lane kernels: %s", hipGetErrorString(e));
             }
             *out = plan;

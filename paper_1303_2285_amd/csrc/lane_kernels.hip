@@ -67,37 +67,86 @@ __device__ __forceinline__ void lmsub(double2 &acc, const double2 x, const doubl
 
 __device__ __forceinline__ double2 dadd(const double2 a, const double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-// One row step: the window sums over the Q column offsets of the entering row
-// (fi, gi) minus, when SLIDE, those of the leaving row (fo, go), added to B.
-// fi/fo: first factors of the row (FP64, LDS broadcast); gi/go: this lane's
-// second factors, already offset by dc (column y of the row at gi[y]).
-template <int QMAX, bool SLIDE>
-__device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, const float2 *gi,
-                                         const double2 *fo, const float2 *go, int Kc, int Q)
+// One block of the row walk: 4 products -- 4 columns of the entering row, or
+// (SLIDE) 2 columns of the entering row and the same 2 of the leaving row.
+// The first factors are LDS broadcasts (every lane reads the same address).
+template <bool SLIDE>
+__device__ __forceinline__ void blk_load(double2 (&f)[4], float2 (&g)[4], const double2 *fi, const float2 *gi,
+                                         const double2 *fo, const float2 *go, int y)
 {
-    double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
-    int y = 0;
-    if (!SLIDE) {
-        for (; y + 4 <= Kc; y += 4) {
-            lmac(s0, fi[y], to_d(gi[y]));
-            lmac(s1, fi[y + 1], to_d(gi[y + 1]));
-            lmac(s2, fi[y + 2], to_d(gi[y + 2]));
-            lmac(s3, fi[y + 3], to_d(gi[y + 3]));
-        }
-        for (; y < Kc; ++y) lmac(s0, fi[y], to_d(gi[y]));
-    } else {
-        for (; y + 2 <= Kc; y += 2) {
-            lmac(s0, fi[y], to_d(gi[y]));
-            lmsub(s1, fo[y], to_d(go[y]));
-            lmac(s2, fi[y + 1], to_d(gi[y + 1]));
-            lmsub(s3, fo[y + 1], to_d(go[y + 1]));
-        }
-        if (y < Kc) {
-            lmac(s0, fi[y], to_d(gi[y]));
-            lmsub(s1, fo[y], to_d(go[y]));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!SLIDE) {
+            f[j] = fi[y + j];
+            g[j] = gi[y + j];
+        } else if (j < 2) {
+            f[j] = fi[y + j];
+            g[j] = gi[y + j];
+        } else {
+            f[j] = fo[y + j - 2];
+            g[j] = go[y + j - 2];
         }
     }
-    double2 S = dadd(dadd(s0, s1), dadd(s2, s3));
+}
+
+template <bool SLIDE>
+__device__ __forceinline__ void blk_prod(double2 (&s)[4], const double2 (&f)[4], const float2 (&g)[4], int j0,
+                                         int j1)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (j < j0 || j >= j1) continue;
+        if (!SLIDE || j < 2)
+            lmac(s[j], f[j], to_d(g[j]));
+        else
+            lmsub(s[j], f[j], to_d(g[j]));
+    }
+}
+
+// One row step: the window sums over the Q column offsets of the entering row
+// minus, when SLIDE, those of the leaving row, added to B.  fi/fo: first
+// factors of the entering / leaving row (FP64 in LDS); gi/go: this lane's
+// second factors, offset by dc (column y at gi[y]).
+//
+// The first window (Kc columns) runs in blocks of 4 products, loaded one
+// block ahead: the first product of a block waits for its loads, then the
+// next block's loads go out, then the other three products run while they
+// arrive.  Two register sets alternate so that nothing is copied.
+template <int QMAX, bool SLIDE>
+__device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, const float2 *gi, const double2 *fo,
+                                         const float2 *go, int Kc, int Q)
+{
+    double2 s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = make_double2(0.0, 0.0);
+    constexpr int step = SLIDE ? 2 : 4;   // columns per block
+    const int nb = Kc / step;
+    if (nb > 0) {
+        double2 fA[4], fB[4];
+        float2 gA[4], gB[4];
+        blk_load<SLIDE>(fA, gA, fi, gi, fo, go, 0);
+        int k = 0;
+        for (; k + 2 <= nb; k += 2) {
+            blk_prod<SLIDE>(s, fA, gA, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            blk_load<SLIDE>(fB, gB, fi, gi, fo, go, (k + 1) * step);
+            __builtin_amdgcn_sched_barrier(0);
+            blk_prod<SLIDE>(s, fA, gA, 1, 4);
+            blk_prod<SLIDE>(s, fB, gB, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            // (the last pass reloads the last block: no branch, so that the
+            // two register sets stay two sets without copies)
+            blk_load<SLIDE>(fA, gA, fi, gi, fo, go, min(k + 2, nb - 1) * step);
+            __builtin_amdgcn_sched_barrier(0);
+            blk_prod<SLIDE>(s, fB, gB, 1, 4);
+        }
+        if (k < nb) blk_prod<SLIDE>(s, fA, gA, 0, 4);
+    }
+    for (int y = nb * step; y < Kc; ++y) {
+        lmac(s[0], fi[y], to_d(gi[y]));
+        if (SLIDE) lmsub(s[1], fo[y], to_d(go[y]));
+    }
+    double2 S = dadd(dadd(s[0], s[1]), dadd(s[2], s[3]));
     B[0] = dadd(B[0], S);
 #pragma unroll
     for (int e = 1; e < QMAX; ++e) {
@@ -147,9 +196,9 @@ template <int QMAX>
 __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_eu(3))) lane_main(LaneArgs la)
 {
     extern __shared__ __align__(16) unsigned char lane_lds[];
-    const int tid = threadIdx.x, nthreads = blockDim.x;
     const int P = la.P, Q = la.Q, N = la.N, M = la.M, Kr = la.Kr, Kc = la.Kc;
     const int ring = la.ring, gstride = la.gstride, rs = la.row_step;
+    const int T = blockDim.x, lt = threadIdx.x;
     float2 *Gi = reinterpret_cast<float2 *>(lane_lds);
     float2 *Go = Gi + (size_t)ring * gstride;
     double2 *Fi = reinterpret_cast<double2 *>(Go + (size_t)ring * gstride);
@@ -164,10 +213,10 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
     const int s_end = rows_walk - 1;          // row step s brings row s into the box
 
     // this lane's combination: dr = 0 with dc in [0, Q), then dr >= 1 with dc in (-Q, Q)
-    const bool live = tid < la.n_lags;
-    int dr = 0, dc = live ? tid : 0;
-    if (live && tid >= Q) {
-        const int u = tid - Q;
+    const bool live = lt < la.n_lags;
+    int dr = 0, dc = live ? lt : 0;
+    if (live && lt >= Q) {
+        const int u = lt - Q;
         dr = 1 + u / (2 * Q - 1);
         dc = u % (2 * Q - 1) - (Q - 1);
     }
@@ -175,15 +224,16 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
     const int j1lo = max(0, -dc), j1hi = Q - max(0, dc);   // column offsets j1 in [j1lo, j1hi)
     const bool diag = dr == 0 && dc == 0;
 
+    // staging, every thread a share
     auto stage_f = [&](double2 *dst, int r_first, int n_rows_) {
-        for (int e = tid; e < n_rows_ * M; e += nthreads) {
+        for (int e = lt; e < n_rows_ * M; e += T) {
             const int rr = e / M, y = e - rr * M;
             dst[e] = to_d(img[(int64_t)(r_first + rr) * la.ld + y]);
         }
     };
     const int gc = M + 2 * Q - 2;
     auto stage_g = [&](float2 *buf, int r_lo, int r_hi) {
-        for (int e = tid; e < (r_hi - r_lo) * gc; e += nthreads) {
+        for (int e = lt; e < (r_hi - r_lo) * gc; e += T) {
             const int rr = e / gc, cc = e - rr * gc;
             const int r = r_lo + rr, y = cc - (Q - 1);
             float2 v = make_float2(0.f, 0.f);
@@ -205,68 +255,76 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
     const int64_t ostep = (int64_t)P * (la.ldr + 1);
     const size_t esz = la.out_fp64 ? 16 : 8;
 
+    // B holds box start t (chain rows): entry row i1 = t - q*rs of every
+    // input q of the chain with 0 <= i1 < P
+    auto emit = [&](int t) {
+        const int q_lo = t >= P ? (t - P + rs) / rs : 0;
+        const int q_hi = min(L - 1, t / rs);
+        for (int q = q_lo; q <= q_hi; ++q) {
+            const int i1 = t - q * rs;
+            if (!live || i1 >= nr) continue;
+            void *Rq = static_cast<char *>(la.R) + ((int64_t)(a0 + q) * la.n_cols + b) * la.r_stride * esz;
+            const int64_t k1 = i1, k2 = i1 + kd;   // at j1 = 0
+            int64_t up = below ? k2 * la.ldr + k1 : k1 * la.ldr + k2;
+            int64_t mir = below ? k1 * la.ldr + k2 : k2 * la.ldr + k1;
+#pragma unroll
+            for (int e = 0; e < QMAX; ++e) {
+                // one entry at a time: the empty asm orders this entry's
+                // division after the previous entry's store, so the divisions
+                // of all offsets are never live at once
+                double2 v = B[e];
+                asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory");
+                if (e >= j1lo && e < j1hi) lane_store(la, Rq, up, mir, v, below, diag);
+                up += ostep;
+                mir += ostep;
+            }
+        }
+    };
+
     int gi_next = 0, go_next = 0;   // next chain row to stage into each ring
-    // Steps [from, to) in chunks: SLIDE steps (s >= Kr) also take away the
-    // row leaving the box.  The two phases are separate loops so that B
-    // passes through one row-step body in each.
+    // Steps [from, to) in chunks.  SLIDE steps (s >= Kr) also take away the
+    // row leaving the box and emit.  The two kinds are separate loops so that
+    // B passes through one row-step body in each.
     auto phase = [&](auto slide_c, int from, int to) {
         constexpr bool SLIDE = decltype(slide_c)::value;
         for (int s0 = from; s0 < to; s0 += kLaneChunk) {
             const int s1 = min(to, s0 + kLaneChunk);
-            // rows entering the box at steps [s0, s1): first factors, and the
-            // second factors of every lag (P - 1 rows further down)
-            stage_f(Fi, s0, s1 - s0);
-            stage_g(Gi, gi_next, s1 + P - 1);
-            gi_next = s1 + P - 1;
-            if (SLIDE) {   // rows leaving the box: Kr rows above
-                stage_f(Fo, s0 - Kr, s1 - s0);
-                stage_g(Go, max(go_next, s0 - Kr), s1 - Kr + P - 1);
-                go_next = s1 - Kr + P - 1;
+            {
+                // rows entering the box at steps [s0, s1): first factors, and
+                // the second factors of every lag (P - 1 rows further down)
+                stage_f(Fi, s0, s1 - s0);
+                stage_g(Gi, gi_next, s1 + P - 1);
+                gi_next = s1 + P - 1;
+                if (SLIDE) {   // rows leaving the box: Kr rows above
+                    stage_f(Fo, s0 - Kr, s1 - s0);
+                    stage_g(Go, max(go_next, s0 - Kr), s1 - Kr + P - 1);
+                    go_next = s1 - Kr + P - 1;
+                }
             }
             __syncthreads();
-            for (int s = s0; s < s1; ++s) {
-                int gs = s % ring + dr;
-                if (gs >= ring) gs -= ring;
-                const float2 *gi = Gi + gs * gstride + (dc + Q - 1);
-                const double2 *fi = Fi + (size_t)(s - s0) * M;
-                if (SLIDE) {
-                    int go_s = (s - Kr) % ring + dr;
-                    if (go_s >= ring) go_s -= ring;
-                    row_step<QMAX, true>(B, fi, gi, Fo + (size_t)(s - s0) * M, Go + go_s * gstride + (dc + Q - 1),
-                                         Kc, Q);
-                } else {
-                    row_step<QMAX, false>(B, fi, gi, nullptr, nullptr, Kc, Q);
-                }
-                if (s < Kr - 1) continue;
-                // B holds box start t (chain rows); it is entry row i1 = t - q*rs
-                // of every input q of the chain with 0 <= i1 < P
-                const int t = s - (Kr - 1);
-                const int q_lo = t >= P ? (t - P + rs) / rs : 0;
-                const int q_hi = min(L - 1, t / rs);
-                for (int q = q_lo; q <= q_hi; ++q) {
-                    const int i1 = t - q * rs;
-                    if (!live || i1 >= nr) continue;
-                    void *Rq = static_cast<char *>(la.R) + ((int64_t)(a0 + q) * la.n_cols + b) * la.r_stride * esz;
-                    const int64_t k1 = i1, k2 = i1 + kd;   // at j1 = 0
-                    int64_t up = below ? k2 * la.ldr + k1 : k1 * la.ldr + k2;
-                    int64_t mir = below ? k1 * la.ldr + k2 : k2 * la.ldr + k1;
-#pragma unroll
-                    for (int e = 0; e < QMAX; ++e) {
-                        // one entry at a time: the empty asm orders this
-                        // entry's division after the previous entry's store,
-                        // so the divisions of all offsets are never live at once
-                        double2 v = B[e];
-                        asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory");
-                        if (e >= j1lo && e < j1hi) lane_store(la, Rq, up, mir, v, below, diag);
-                        up += ostep;
-                        mir += ostep;
+            {
+                for (int s = s0; s < s1; ++s) {
+                    int gs = s % ring + dr;
+                    if (gs >= ring) gs -= ring;
+                    const float2 *gi = Gi + gs * gstride + (dc + Q - 1);
+                    const double2 *fi = Fi + (size_t)(s - s0) * M;
+                    if (SLIDE) {
+                        int go_s = (s - Kr) % ring + dr;
+                        if (go_s >= ring) go_s -= ring;
+                        row_step<QMAX, true>(B, fi, gi, Fo + (size_t)(s - s0) * M,
+                                             Go + go_s * gstride + (dc + Q - 1), Kc, Q);
+                        emit(s - (Kr - 1));
+                    } else {
+                        row_step<QMAX, false>(B, fi, gi, nullptr, nullptr, Kc, Q);
                     }
                 }
             }
             __syncthreads();
         }
     };
+
     phase(std::integral_constant<bool, false>{}, 0, Kr);
+    emit(0);
     phase(std::integral_constant<bool, true>{}, Kr, s_end + 1);
 }
 

@@ -46,8 +46,8 @@ def model(img, N, M, P, Q, rs, cs, n_rows, n_cols, chain=None, fill_full=True, c
     ring, gstride, CH, L0 = info["ring"], info["gstride"], info["chunk"], info["chain"]
     PQ, Kr, Kc = P * Q, N - P + 1, M - Q + 1
     n_lags = PQ + (P - 1) * (Q - 1)
-    threads = info["threads"]
-    assert threads == -(-n_lags // 64) * 64
+    threads = -(-n_lags // 64) * 64
+    assert info["threads"] == threads
     # LDS: two rings of complex64 rows, two chunks of FP64 first-factor rows
     assert info["lds"] == 2 * ring * gstride * 8 + 2 * CH * M * 16
     assert gstride >= M + 2 * Q - 2 and ring == CH + P - 1
@@ -66,7 +66,6 @@ def model(img, N, M, P, Q, rs, cs, n_rows, n_cols, chain=None, fill_full=True, c
         if not check_only:
             padded[:rows_walk, Q - 1:Q - 1 + M] = img[r0:r0 + rows_walk, c0:c0 + M]
         ring_row = {"i": [-1] * ring, "o": [-1] * ring}
-        B = np.zeros((threads, Q), dtype=np.complex128)
         nxt = {"i": 0, "o": 0}
 
         def stage(which, lo, hi, oldest_needed):
@@ -77,60 +76,68 @@ def model(img, N, M, P, Q, rs, cs, n_rows, n_cols, chain=None, fill_full=True, c
                 assert prev < oldest_needed, "a ring row still in use is overwritten"
                 ring_row[which][slot] = r
 
-        for slide, frm, to in ((False, 0, Kr), (True, Kr, rows_walk)):
+        def walk(B, ring_in, s, slide):
+            """one row step of every lane: ring checks, then the window sums"""
+            for t, (dr, dc, live) in enumerate(lags):
+                gs = s % ring + dr
+                gs -= ring if gs >= ring else 0
+                assert 0 <= gs < ring and ring_row[ring_in][gs] == s + dr
+                assert 0 <= dc + Q - 1 and dc + Q - 1 + M - 1 < gstride
+                if slide:
+                    go = (s - Kr) % ring + dr
+                    go -= ring if go >= ring else 0
+                    assert ring_row["o"][go] == s - Kr + dr
+                if check_only:
+                    continue
+                z = padded[s, Q - 1:Q - 1 + M] * np.conj(padded[s + dr, Q - 1 + dc:Q - 1 + dc + M])
+                if slide:
+                    z = z - padded[s - Kr, Q - 1:Q - 1 + M] * np.conj(
+                        padded[s - Kr + dr, Q - 1 + dc:Q - 1 + dc + M])
+                c = np.concatenate([[0], np.cumsum(z)])
+                B[t] += c[Kc:Kc + Q] - c[0:Q]
+
+        def emit(B, tt):
+            q_lo = (tt - P + rs) // rs if tt >= P else 0
+            q_hi = min(L - 1, tt // rs)
+            for q in range(q_lo, q_hi + 1):
+                i1 = tt - q * rs
+                assert 0 <= i1 < P
+                for t, (dr, dc, live) in enumerate(lags):
+                    if not live or i1 >= P - dr:
+                        continue
+                    for e in range(max(0, -dc), Q - max(0, dc)):
+                        k1, k2 = i1 + P * e, i1 + dr + P * (e + dc)
+                        v = B[t, e]
+                        if dr == 0 and dc == 0:
+                            v = complex(v.real, 0.0)
+                        u1, u2 = (k2, k1) if k1 > k2 else (k1, k2)
+                        vu = np.conj(v) if k1 > k2 else v
+                        R[a0 + q, b, u1, u2] = vu
+                        writes[a0 + q, b, u1, u2] += 1
+                        if fill_full and u1 != u2:
+                            R[a0 + q, b, u2, u1] = np.conj(vu)
+                            writes[a0 + q, b, u2, u1] += 1
+
+        def seed(B, which, frm, to):
             for s0 in range(frm, to, CH):
                 s1 = min(to, s0 + CH)
-                assert s1 - s0 <= CH
-                stage("i", nxt["i"], s1 + P - 1, s0)
-                nxt["i"] = s1 + P - 1
-                if slide:
-                    stage("o", max(nxt["o"], s0 - Kr), s1 - Kr + P - 1, s0 - Kr)
-                    nxt["o"] = s1 - Kr + P - 1
+                stage(which, nxt[which], s1 + P - 1, s0)
+                nxt[which] = s1 + P - 1
                 for s in range(s0, s1):
-                    rows_in = []
-                    for t, (dr, dc, live) in enumerate(lags):
-                        gs = s % ring + dr
-                        gs -= ring if gs >= ring else 0
-                        assert 0 <= gs < ring and ring_row["i"][gs] == s + dr
-                        base = dc + Q - 1
-                        assert 0 <= base and base + M - 1 < gstride
-                        if slide:
-                            go = (s - Kr) % ring + dr
-                            go -= ring if go >= ring else 0
-                            assert ring_row["o"][go] == s - Kr + dr
-                        rows_in.append((dr, dc))
-                    if not check_only:
-                        fi = padded[s, Q - 1:Q - 1 + M]
-                        for t, (dr, dc) in enumerate(rows_in):
-                            z = fi * np.conj(padded[s + dr, Q - 1 + dc:Q - 1 + dc + M])
-                            if slide:
-                                fo = padded[s - Kr, Q - 1:Q - 1 + M]
-                                z = z - fo * np.conj(padded[s - Kr + dr, Q - 1 + dc:Q - 1 + dc + M])
-                            c = np.concatenate([[0], np.cumsum(z)])
-                            B[t] += c[Kc:Kc + Q] - c[0:Q]
-                    if s < Kr - 1:
-                        continue
-                    tt = s - (Kr - 1)
-                    q_lo = (tt - P + rs) // rs if tt >= P else 0
-                    q_hi = min(L - 1, tt // rs)
-                    for q in range(q_lo, q_hi + 1):
-                        i1 = tt - q * rs
-                        assert 0 <= i1 < P
-                        for t, (dr, dc, live) in enumerate(lags):
-                            if not live or i1 >= P - dr:
-                                continue
-                            for e in range(max(0, -dc), Q - max(0, dc)):
-                                k1, k2 = i1 + P * e, i1 + dr + P * (e + dc)
-                                v = B[t, e]
-                                if dr == 0 and dc == 0:
-                                    v = complex(v.real, 0.0)
-                                u1, u2 = (k2, k1) if k1 > k2 else (k1, k2)
-                                vu = np.conj(v) if k1 > k2 else v
-                                R[a0 + q, b, u1, u2] = vu
-                                writes[a0 + q, b, u1, u2] += 1
-                                if fill_full and u1 != u2:
-                                    R[a0 + q, b, u2, u1] = np.conj(vu)
-                                    writes[a0 + q, b, u2, u1] += 1
+                    walk(B, which, s, False)
+
+        B = np.zeros((threads, Q), dtype=np.complex128)
+        seed(B, "i", 0, Kr)
+        emit(B, 0)
+        for s0 in range(Kr, rows_walk, CH):
+            s1 = min(rows_walk, s0 + CH)
+            stage("i", nxt["i"], s1 + P - 1, s0)
+            nxt["i"] = s1 + P - 1
+            stage("o", max(nxt["o"], s0 - Kr), s1 - Kr + P - 1, s0 - Kr)
+            nxt["o"] = s1 - Kr + P - 1
+            for s in range(s0, s1):
+                walk(B, "i", s, True)
+                emit(B, s - (Kr - 1))
     iu = np.triu_indices(PQ)
     assert np.all(writes[:, :, iu[0], iu[1]] == 1), "an upper-triangle entry is not written exactly once"
     if fill_full:
