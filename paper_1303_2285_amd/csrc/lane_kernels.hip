@@ -46,6 +46,15 @@ namespace covest {
 namespace {
 
 __device__ __forceinline__ double2 to_d(const float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ double2 to_d(const double2 v) { return v; }
+
+// Element types of the staged first-factor rows and second-factor rings
+// (sizes kLaneFBytes, kLaneGBytes).
+typedef double2 fstage_t;
+typedef float2 gstage_t;
+static_assert(sizeof(fstage_t) == kLaneFBytes && sizeof(gstage_t) == kLaneGBytes, "LDS element sizes");
+__device__ __forceinline__ void put(double2 &d, const float2 v) { d = to_d(v); }
+__device__ __forceinline__ void put(float2 &d, const float2 v) { d = v; }
 
 // acc += x * conj(y)
 __device__ __forceinline__ void lmac(double2 &acc, const double2 x, const double2 y)
@@ -71,8 +80,8 @@ __device__ __forceinline__ double2 dadd(const double2 a, const double2 b) { retu
 // (SLIDE) 2 columns of the entering row and the same 2 of the leaving row.
 // The first factors are LDS broadcasts (every lane reads the same address).
 template <bool SLIDE>
-__device__ __forceinline__ void blk_load(double2 (&f)[4], float2 (&g)[4], const double2 *fi, const float2 *gi,
-                                         const double2 *fo, const float2 *go, int y)
+__device__ __forceinline__ void blk_load(fstage_t (&f)[4], gstage_t (&g)[4], const fstage_t *fi, const gstage_t *gi,
+                                         const fstage_t *fo, const gstage_t *go, int y)
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -90,16 +99,16 @@ __device__ __forceinline__ void blk_load(double2 (&f)[4], float2 (&g)[4], const 
 }
 
 template <bool SLIDE>
-__device__ __forceinline__ void blk_prod(double2 (&s)[4], const double2 (&f)[4], const float2 (&g)[4], int j0,
+__device__ __forceinline__ void blk_prod(double2 (&s)[4], const fstage_t (&f)[4], const gstage_t (&g)[4], int j0,
                                          int j1)
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (j < j0 || j >= j1) continue;
         if (!SLIDE || j < 2)
-            lmac(s[j], f[j], to_d(g[j]));
+            lmac(s[j], to_d(f[j]), to_d(g[j]));
         else
-            lmsub(s[j], f[j], to_d(g[j]));
+            lmsub(s[j], to_d(f[j]), to_d(g[j]));
     }
 }
 
@@ -113,8 +122,8 @@ __device__ __forceinline__ void blk_prod(double2 (&s)[4], const double2 (&f)[4],
 // next block's loads go out, then the other three products run while they
 // arrive.  Two register sets alternate so that nothing is copied.
 template <int QMAX, bool SLIDE>
-__device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, const float2 *gi, const double2 *fo,
-                                         const float2 *go, int Kc, int Q)
+__device__ __forceinline__ void row_step(double2 (&B)[QMAX], const fstage_t *fi, const gstage_t *gi, const fstage_t *fo,
+                                         const gstage_t *go, int Kc, int Q)
 {
     double2 s[4];
 #pragma unroll
@@ -122,8 +131,8 @@ __device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, 
     constexpr int step = SLIDE ? 2 : 4;   // columns per block
     const int nb = Kc / step;
     if (nb > 0) {
-        double2 fA[4], fB[4];
-        float2 gA[4], gB[4];
+        fstage_t fA[4], fB[4];
+        gstage_t gA[4], gB[4];
         blk_load<SLIDE>(fA, gA, fi, gi, fo, go, 0);
         int k = 0;
         for (; k + 2 <= nb; k += 2) {
@@ -143,8 +152,8 @@ __device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, 
         if (k < nb) blk_prod<SLIDE>(s, fA, gA, 0, 4);
     }
     for (int y = nb * step; y < Kc; ++y) {
-        lmac(s[0], fi[y], to_d(gi[y]));
-        if (SLIDE) lmsub(s[1], fo[y], to_d(go[y]));
+        lmac(s[0], to_d(fi[y]), to_d(gi[y]));
+        if (SLIDE) lmsub(s[1], to_d(fo[y]), to_d(go[y]));
     }
     double2 S = dadd(dadd(s[0], s[1]), dadd(s[2], s[3]));
     B[0] = dadd(B[0], S);
@@ -152,11 +161,11 @@ __device__ __forceinline__ void row_step(double2 (&B)[QMAX], const double2 *fi, 
     for (int e = 1; e < QMAX; ++e) {
         if (e < Q) {
             const int yi = Kc - 1 + e, yo = e - 1;   // column entering and column leaving the window
-            lmac(S, fi[yi], to_d(gi[yi]));
-            lmsub(S, fi[yo], to_d(gi[yo]));
+            lmac(S, to_d(fi[yi]), to_d(gi[yi]));
+            lmsub(S, to_d(fi[yo]), to_d(gi[yo]));
             if (SLIDE) {
-                lmsub(S, fo[yi], to_d(go[yi]));
-                lmac(S, fo[yo], to_d(go[yo]));
+                lmsub(S, to_d(fo[yi]), to_d(go[yi]));
+                lmac(S, to_d(fo[yo]), to_d(go[yo]));
             }
             B[e] = dadd(B[e], S);
         }
@@ -199,10 +208,10 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
     const int P = la.P, Q = la.Q, N = la.N, M = la.M, Kr = la.Kr, Kc = la.Kc;
     const int ring = la.ring, gstride = la.gstride, rs = la.row_step;
     const int T = blockDim.x, lt = threadIdx.x;
-    float2 *Gi = reinterpret_cast<float2 *>(lane_lds);
-    float2 *Go = Gi + (size_t)ring * gstride;
-    double2 *Fi = reinterpret_cast<double2 *>(Go + (size_t)ring * gstride);
-    double2 *Fo = Fi + (size_t)kLaneChunk * M;
+    gstage_t *Gi = reinterpret_cast<gstage_t *>(lane_lds);
+    gstage_t *Go = Gi + (size_t)ring * gstride;
+    fstage_t *Fi = reinterpret_cast<fstage_t *>(Go + (size_t)ring * gstride);
+    fstage_t *Fo = Fi + (size_t)kLaneChunk * M;
 
     // workgroup -> (chain, grid column)
     const int wg = xcd_block(blockIdx.x, gridDim.x);
@@ -225,20 +234,20 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
     const bool diag = dr == 0 && dc == 0;
 
     // staging, every thread a share
-    auto stage_f = [&](double2 *dst, int r_first, int n_rows_) {
+    auto stage_f = [&](fstage_t *dst, int r_first, int n_rows_) {
         for (int e = lt; e < n_rows_ * M; e += T) {
             const int rr = e / M, y = e - rr * M;
-            dst[e] = to_d(img[(int64_t)(r_first + rr) * la.ld + y]);
+            put(dst[e], img[(int64_t)(r_first + rr) * la.ld + y]);
         }
     };
     const int gc = M + 2 * Q - 2;
-    auto stage_g = [&](float2 *buf, int r_lo, int r_hi) {
+    auto stage_g = [&](gstage_t *buf, int r_lo, int r_hi) {
         for (int e = lt; e < (r_hi - r_lo) * gc; e += T) {
             const int rr = e / gc, cc = e - rr * gc;
             const int r = r_lo + rr, y = cc - (Q - 1);
             float2 v = make_float2(0.f, 0.f);
             if (r < rows_walk && y >= 0 && y < M) v = img[(int64_t)r * la.ld + y];
-            buf[(r % ring) * gstride + cc] = v;
+            put(buf[(r % ring) * gstride + cc], v);
         }
     };
 
@@ -306,8 +315,8 @@ __global__ void __launch_bounds__(kLaneMaxLags) __attribute__((amdgpu_waves_per_
                 for (int s = s0; s < s1; ++s) {
                     int gs = s % ring + dr;
                     if (gs >= ring) gs -= ring;
-                    const float2 *gi = Gi + gs * gstride + (dc + Q - 1);
-                    const double2 *fi = Fi + (size_t)(s - s0) * M;
+                    const gstage_t *gi = Gi + gs * gstride + (dc + Q - 1);
+                    const fstage_t *fi = Fi + (size_t)(s - s0) * M;
                     if (SLIDE) {
                         int go_s = (s - Kr) % ring + dr;
                         if (go_s >= ring) go_s -= ring;

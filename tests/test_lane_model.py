@@ -1,7 +1,7 @@
 """CPU model of the lane engine (one lane per unique combination), no GPU.
 
 `covest_lane_plan_get` gives the plan the library launches: second-factor
-rings of `ring` rows with a row stride of `gstride` complex64 elements,
+rings of `ring` rows with a row stride of `gstride` elements,
 chunks of `chunk` row steps, `chain` inputs per workgroup along a grid
 column.  The model replays `lane_main` with that plan -- the staging of rows
 into the rings (which ring slot holds which row of the chain at every row
@@ -48,7 +48,7 @@ def model(img, N, M, P, Q, rs, cs, n_rows, n_cols, chain=None, fill_full=True, c
     n_lags = PQ + (P - 1) * (Q - 1)
     threads = -(-n_lags // 64) * 64
     assert info["threads"] == threads
-    # LDS: two rings of complex64 rows, two chunks of FP64 first-factor rows
+    # LDS: two rings of complex64 second-factor rows, two chunks of FP64 first-factor rows
     assert info["lds"] == 2 * ring * gstride * 8 + 2 * CH * M * 16
     assert gstride >= M + 2 * Q - 2 and ring == CH + P - 1
     lags = _lags(P, Q, n_lags, threads)
