@@ -245,7 +245,7 @@ def test_workspace_too_small(cv, torch_dev):
 
 
 @pytest.mark.parametrize("bad", ["nan", "inf"])
-@pytest.mark.parametrize("engine", ["matrix", "vector"])
+@pytest.mark.parametrize("engine", ["matrix", "vector", "lane"])
 @pytest.mark.parametrize("shape", [(64, 64, 8, 8), (90, 70, 12, 9)], ids=lambda s: "x".join(map(str, s)))
 def test_non_finite_input(cv, torch_dev, oracle_mod, shape, engine, bad):
     """Non-finite elements at a corner, on an edge and in the interior of an

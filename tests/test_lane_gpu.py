@@ -85,6 +85,32 @@ def test_single_input_integer_bit_exact(cv, torch_dev, oracle_mod, shape):
     assert np.array_equal(R.cpu().numpy(), oracle_mod.forward(A, P, Q))
 
 
+EDGE_SHAPES = [
+    (1, 1, 1, 1), (5, 7, 5, 7), (5, 7, 1, 1), (9, 4, 3, 4), (33, 17, 1, 16), (17, 33, 16, 1),
+    (40, 33, 4, 16), (97, 131, 12, 4), (131, 97, 5, 13), (64, 64, 32, 32), (70, 66, 33, 2),
+    (200, 150, 20, 24), (128, 256, 16, 8), (300, 64, 16, 12), (48, 48, 8, 8), (130, 130, 40, 40),
+]
+
+
+@pytest.mark.parametrize("shape", EDGE_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_edge_shapes_or_refusal(cv, torch_dev, oracle_mod, shape):
+    """The recurrence's edge shapes on the lane engine: bit-exact where its plan
+    fits, COVEST_ERR_UNSUPPORTED (before any device work) where it does not."""
+    torch, dev = torch_dev
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N * 1000 + M * 10 + P + Q)
+    At = torch.from_numpy(A).to(dev)
+    if not cv.lane_plan(N, M, P, Q)["fits"]:
+        with pytest.raises(cv.CovestError) as ei:
+            cv.covest_forward(At, P, Q, engine="lane")
+        assert ei.value.status == cv.ERR_UNSUPPORTED
+        return
+    _note("lane edge", shape)
+    R = cv.covest_forward(At, P, Q, engine="lane").cpu().numpy()
+    ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
+
+
 def test_single_input_options(cv, torch_dev, oracle_mod):
     """Float input: FP64 to 1e-12, FP32 output within one rounding, the upper
     fill leaves the lower triangle alone, normalize=0 gives the sums, and a
