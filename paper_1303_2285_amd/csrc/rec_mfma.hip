@@ -17,12 +17,19 @@
 // every product x[c] * conj(y) is formed once, as in the paper's method
 // (Sec. 3.3), not once per output entry.
 //
-// Complex arithmetic: the four real parts of a complex multiply-add are four
-// real products over the same 4 positions,
-//     Re T += yr*xr + yi*xi,      Im T += yr*xi + yi*(-xr),
-// i.e. four MFMAs per 16 x 16 tile pair per k-group.  Operands come straight
-// from A (complex64) and are widened to FP64 in registers; products of two
-// floats are exact in FP64, sums accumulate in FP64 inside the matrix core.
+// Complex arithmetic: conj(y) * x over 4 positions takes three real products
+// (the three-multiplication form of a complex product):
+//     K1 += (yr - yi) * xr,   K2 += yr * (xi - xr),   K3 += (-yi) * (xr + xi),
+//     Re T = K1 - K3 = sum yr*xr + yi*xi,   Im T = K1 + K2 = sum yr*xi - yi*xr,
+// i.e. three MFMAs per 16 x 16 tile per k-group, into three accumulators that
+// are combined once per job.  Lag blocks of more than 4 tile rows keep the
+// four-product form (Re += yr*xr + yi*xi, Im += yr*xi + yi*(-xr)) in two
+// accumulators, which their registers allow; blocks of up to 4 rows run
+// their tile columns in passes small enough for three accumulators.
+// Operands come straight from A (complex64) and are widened to FP64 in
+// registers; a product of two floats, and of a float and a sum or difference
+// of two floats, is exact in FP64 (the sum is, for parts within 2^28 of each
+// other), and sums accumulate in FP64 inside the matrix core.
 //
 // MFMA lane layout of v_mfma_f64_16x16x4 (gfx950): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; result register r of lane l holds D[l/16 + 4r][l%16].
@@ -58,10 +65,11 @@ __device__ __forceinline__ bool unique_lag(const Inst &in, int d1, int d2, int &
     return dc >= 0 && dc < in.Q && dr > -in.P && dr < in.P && (dc > 0 || dr >= 0);
 }
 
-// Widen 4 positions of the operands and return the 4 MFMAs per tile pair
-// that add them (issued by the caller after the next loads).
+// Widen 4 positions of the operands and return the MFMAs that add them
+// (issued by the caller after the next loads).  Four-product form: two
+// accumulators per tile (Re, Im).
 template <int MT, int NT>
-__device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const float2 (&xn)[NT])
+__device__ __forceinline__ auto kgroup_products4(const float2 (&an)[MT], const float2 (&xn)[NT])
 {
     double yr[MT], yi[MT], xr[NT], xi[NT], nxr[NT];
 #pragma unroll
@@ -93,14 +101,53 @@ __device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const fl
     };
 }
 
+// Three-product form: three accumulators per tile (K1, K2, K3).
+template <int MT, int NT>
+__device__ __forceinline__ auto kgroup_products3(const float2 (&an)[MT], const float2 (&xn)[NT])
+{
+    double sy[MT], yr[MT], nyi[MT], xr[NT], dmc[NT], cpd[NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        yr[m] = (double)an[m].x;
+        nyi[m] = (double)(-an[m].y);
+        sy[m] = yr[m] + nyi[m];
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        xr[n] = (double)xn[n].x;
+        const double xi = (double)xn[n].y;
+        dmc[n] = xi - xr[n];
+        cpd[n] = xr[n] + xi;
+    }
+    return [=](v4d (&acc)[MT * NT][3]) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[m * NT + n][0] = mfma64(sy[m], xr[n], acc[m * NT + n][0]);
+                acc[m * NT + n][1] = mfma64(yr[m], dmc[n], acc[m * NT + n][1]);
+                acc[m * NT + n][2] = mfma64(nyi[m], cpd[n], acc[m * NT + n][2]);
+            }
+    };
+}
+
+template <int MT, int NT, int C>
+__device__ __forceinline__ auto kgroup_products(const float2 (&an)[MT], const float2 (&xn)[NT])
+{
+    if constexpr (C == 3)
+        return kgroup_products3<MT, NT>(an, xn);
+    else
+        return kgroup_products4<MT, NT>(an, xn);
+}
+
 // Run k-groups [k_a, k_b): the loads of k-group kg + D are issued before
 // kg's products, so they overlap (the last iterations reload the last
 // k-group: harmless); the scheduling barriers keep the compiler from moving
 // the loads back behind the conversions.  A k-group of MT * NT tiles takes
-// 4 MT NT MFMAs, so small lag blocks keep more k-groups in flight (D) to
+// 3 or 4 MT NT MFMAs, so small lag blocks keep more k-groups in flight (D) to
 // cover the load latency.
-template <int MT, int NT, class Load>
-__device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][2], Load load)
+template <int MT, int NT, int C, class Load>
+__device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT][C], Load load)
 {
     // an empty range loads nothing (its first load would be k-group k_a - 1)
     if (k_a >= k_b) return;
@@ -112,7 +159,7 @@ __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (D == 1 || kg + d < k_b) {
-                auto mf = kgroup_products<MT, NT>(an[d], xn[d]);
+                auto mf = kgroup_products<MT, NT, C>(an[d], xn[d]);
                 __builtin_amdgcn_sched_barrier(0);
                 load(min(kg + d + D, k_b - 1), an[d], xn[d]);
                 __builtin_amdgcn_sched_barrier(0);
@@ -134,8 +181,8 @@ __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT
 // are staged per wave in LDS, kMXCap of them at a time, and read from there.
 // The planner sets job.kin, the k-groups that need no clamp: 0 for a line of
 // fewer than 4 positions past k0.
-template <int MT, int NT, int OR>
-__device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
+template <int MT, int NT, int OR, int C>
+__device__ __forceinline__ void mfma_pass(const MJob &job, const Inst &in, double *red, int d2shift)
 {
     constexpr int T = MT * NT;
     constexpr int span = 16 * NT - 1;      // lane lags d2 in [d2lo, d2lo + span]
@@ -151,13 +198,15 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     const int nlines = OR ? in.M : in.N;
     const int npos = OR ? in.N : in.M;
     const int d1lo = OR ? 0 : -(in.P - 1);
-    const int d2lo = OR ? -(in.P - 1) : 0;
+    const int d2lo = (OR ? -(in.P - 1) : 0) + d2shift;
     // k-groups whose 4 positions all lie inside A (the planner counts them)
     const int kin = job.kin;
 
-    v4d acc[T][2];
+    v4d acc[T][C];
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t][0] = acc[t][1] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[t][c] = (v4d){0.0, 0.0, 0.0, 0.0};
     float2 *xb = reinterpret_cast<float2 *>(red) + wave * kMXCap;
     const int chunk = (kMXCap - span) / 4;   // k-groups per staged chunk
 
@@ -212,7 +261,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
                 for (int n = 0; n < NT; ++n) xn[n] = xl[4 * (kg - kc) - 16 * n];
             };
             const int kplain = min(kce, kin);
-            run_kgroups<MT, NT>(kc, kplain, acc,
+            run_kgroups<MT, NT, C>(kc, kplain, acc,
                                 [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, aoff, an, xn); });
             if (kplain < kce) {
                 // the last k-group of a line can pass A's last position: clamp
@@ -223,9 +272,22 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     off[m] = (uint32_t)q[m] * ls + (uint32_t)(min(pos, npos - 1) - (job.k0 + 4 * kplain)) * ps;
-                run_kgroups<MT, NT>(kplain, kce, acc,
+                run_kgroups<MT, NT, C>(kplain, kce, acc,
                                     [&](int kg, float2(&an)[MT], float2(&xn)[NT]) { load(kg, off, an, xn); });
             }
+        }
+    }
+
+    // Re and Im of every tile
+    v4d res[T][2];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        if constexpr (C == 3) {
+            res[t][0] = acc[t][0] - acc[t][2];
+            res[t][1] = acc[t][0] + acc[t][1];
+        } else {
+            res[t][0] = acc[t][0];
+            res[t][1] = acc[t][1];
         }
     }
 
@@ -249,7 +311,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
         if (line < job.line_end) {
             double *z = OR ? in.zc : in.zr;
             write_row(reinterpret_cast<double2 *>(z + (int64_t)(job.out + wave) * in.lag_stride * 2),
-                      [&](int t, int c, int r) { return acc[t][c][r]; });
+                      [&](int t, int c, int r) { return res[t][c][r]; });
         }
         return;
     }
@@ -269,7 +331,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) at(wave - 4, t, c, r) = acc[t][c][r];
+                for (int r = 0; r < 4; ++r) at(wave - 4, t, c, r) = res[t][c][r];
     }
     __syncthreads();
     if (wave < 4) {
@@ -278,7 +340,7 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) at(wave, t, c, r) = at(wave, t, c, r) + acc[t][c][r];
+                for (int r = 0; r < 4; ++r) at(wave, t, c, r) = at(wave, t, c, r) + res[t][c][r];
     }
     __syncthreads();
     if (wave < 2) {
@@ -293,6 +355,29 @@ __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double
     if (wave == 0)
         write_row(reinterpret_cast<double2 *>(in.partial + (int64_t)job.out * in.lag_stride * 2),
                   [&](int t, int c, int r) { return at(0, t, c, r) + at(1, t, c, r); });
+}
+
+// A job in passes over its tile columns: lag blocks of at most 4 tile rows
+// take the three-product form with passes of NP columns (3 MT NP <= 12
+// accumulators, the registers of the four-product form's 8 tiles), larger
+// blocks the four-product form in one pass.  Passes restage their lines and
+// reload their first operands; they share nothing else.
+template <int MT, int NT>
+struct MfmaPasses {
+    static constexpr int C = MT <= 4 ? 3 : 2;
+    static constexpr int NP = C == 2 ? NT : (MT * NT <= 4 ? NT : (NT % 2 == 0 && MT * (NT / 2) <= 4) ? NT / 2 : 1);
+};
+
+template <int MT, int NT, int OR>
+__device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
+{
+    using PS = MfmaPasses<MT, NT>;
+    static_assert(NT % PS::NP == 0, "passes cover the tile columns");
+#pragma unroll 1
+    for (int n0 = 0; n0 < NT; n0 += PS::NP) {
+        if (n0 > 0) __syncthreads();   // the previous pass's LDS reads are done
+        mfma_pass<MT, PS::NP, OR, PS::C>(job, in, red, 16 * n0);
+    }
 }
 
 // One workgroup per job; orientation-1 jobs use the transposed tile shape
