@@ -654,6 +654,13 @@ struct AdjGeom {
     int ir0, ir1, ic0, ic1, ndc, n_lags, interior_blocks;
     int64_t frame_jobs;
     size_t lds_tables, lds_interior, ws_bytes;
+    // matrix-core interior (windows up to 16 x 16 with an interior)
+    bool mfma;
+    int ny, nx, mtiles, mranges;
+    size_t lds_frame;   // LDS of the frame's launch
+    // workspace byte offsets: prefix tables, full sums, line-job weights,
+    // boundary rows of the matrix-core interior
+    size_t off_tables, off_hfull, off_wrows, off_wcols, off_bnd;
 };
 
 AdjGeom adj_geometry(int N, int M, int P, int Q)
@@ -684,7 +691,33 @@ AdjGeom adj_geometry(int N, int M, int P, int Q)
     const int64_t nbr = N - (g.ir1 - g.ir0), nbc = M - (g.ic1 - g.ic0);
     g.frame_jobs = nbr * ((g.ic1 - g.ic0 + kAdjFL - 1) / kAdjFL) + nbc * ((g.ir1 - g.ir0 + kAdjFL - 1) / kAdjFL) +
                    nbr * nbc;
-    g.ws_bytes = (size_t)g.n_lags * (P + 1) * (Q + 1) * 16 + (size_t)g.n_lags * 16;
+    size_t off = 0;
+    g.off_tables = off;
+    off += (size_t)g.n_lags * (P + 1) * (Q + 1) * 16;
+    g.off_hfull = off;
+    off += (size_t)g.n_lags * 16;
+    g.off_wrows = off;
+    g.off_wcols = off;
+    if (interior) {
+        off += (size_t)nbr * g.n_lags * 16;
+        g.off_wcols = off;
+        off += (size_t)nbc * g.n_lags * 16;
+    }
+    g.off_bnd = off;
+    g.ws_bytes = off;
+    g.mfma = interior && P <= kAdjMMaxWin && Q <= kAdjMMaxWin;
+    if (g.mfma) {
+        g.ny = g.ir1 - g.ir0;
+        g.nx = g.ic1 - g.ic0;
+        g.mtiles = (g.nx + 15) / 16;
+        g.mranges = (N + kAdjMSpan - 1) / kAdjMSpan;
+        g.ws_bytes += (size_t)(g.mranges - 1) * 2 * (2 * P - 2) * 16 * g.mtiles * 16;
+        // the frame: every weight row of the wider line kind in one slab (at
+        // most 32 rows), and at least the corner jobs' 256-entry sum
+        const size_t row_slab = (size_t)std::min(2 * P - 1, 32) * adj_line_row_bytes(2 * Q - 1);
+        const size_t col_slab = (size_t)std::min(2 * Q - 1, 32) * adj_line_row_bytes(2 * P - 1);
+        g.lds_frame = std::min<size_t>(kAdjFrameLds, std::max<size_t>({256 * 16, row_slab, col_slab}));
+    }
     return g;
 }
 
@@ -1415,9 +1448,23 @@ int covest_backward_ex(const void *A, int64_t lda, const void *dR, int64_t ldr, 
     aa.ic0 = g.ic0;
     aa.ic1 = g.ic1;
     aa.ndc = g.ndc;
-    aa.tables = static_cast<double *>(ws);
-    aa.hfull = aa.tables + (size_t)2 * g.n_lags * (P + 1) * (Q + 1);
+    char *wsb = static_cast<char *>(ws);
+    aa.tables = reinterpret_cast<double *>(wsb + g.off_tables);
+    aa.hfull = reinterpret_cast<double *>(wsb + g.off_hfull);
+    aa.wrows = reinterpret_cast<double *>(wsb + g.off_wrows);
+    aa.wcols = reinterpret_cast<double *>(wsb + g.off_wcols);
     aa.normalize = o.normalize ? 1 : 0;
+    if (g.mfma) {
+        aa.ny = g.ny;
+        aa.nx = g.nx;
+        aa.mtiles = g.mtiles;
+        aa.mranges = g.mranges;
+        aa.bnd = reinterpret_cast<double *>(wsb + g.off_bnd);
+        HIP_TRY(timed("adjoint", stream, [&] {
+            return launch_adjoint_mfma(aa, g.n_lags, g.lds_tables, g.frame_jobs, g.lds_frame, stream);
+        }));
+        return finish_call(stream);
+    }
     HIP_TRY(timed("adjoint", stream, [&] {
         return launch_adjoint(aa, g.n_lags, g.lds_tables, g.interior_blocks, g.lds_interior, g.frame_jobs, stream);
     }));

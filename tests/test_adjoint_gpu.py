@@ -268,3 +268,30 @@ def test_adjoint_strided_views(cv, tdev, oracle_mod, precision, tol):
     mask = np.ones(o.shape, bool)
     mask[1:1 + N, 4:4 + M] = False
     assert np.all(o[mask] == 7.0 + 7.0j)
+
+
+INT_SHAPES = [(9, 11, 3, 4), (70, 50, 16, 12), (150, 70, 9, 13), (200, 90, 16, 16), (65, 40, 16, 16),
+              (130, 37, 1, 5), (129, 20, 2, 1), (97, 47, 16, 1), (300, 40, 20, 3), (100, 90, 32, 32)]
+
+
+@pytest.mark.parametrize("shape", INT_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_integer_exact(cv, tdev, oracle_mod, shape):
+    """Small-integer A and dR, FP64, no normalization: every sum is an integer
+    below 2^53, so the interior (matrix cores for windows up to 16 x 16,
+    including the output rows two input spans share; vector units above) and
+    the frame reproduce the oracle's adjoint bit for bit."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N * 11 + M + P)
+    rng = np.random.default_rng(N + 17 * M + Q)
+    PQ = P * Q
+    G = (rng.integers(-4, 5, (PQ, PQ)) + 1j * rng.integers(-4, 5, (PQ, PQ))).astype(np.complex128)
+    _note("adjoint integer exact", shape)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q, normalize=False)
+    torch.cuda.synchronize()
+    got = dA.cpu().numpy()
+    if PQ <= 256:
+        ref = oracle_mod.adjoint(A, G, P, Q, normalize=False)
+    else:
+        ref = oracle_mod.adjoint_blas(A, G, P, Q, normalize=False)
+    assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag)
