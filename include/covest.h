@@ -34,7 +34,11 @@
  *     further entries of the same combination NaN as well; every entry it
  *     returns finite is the definition's value.  For the plain (Hankel) form
  *     only the propagation is stated: which entries turn non-finite depends
- *     on its tiling.
+ *     on its tiling.  The adjoint makes non-finite every element of every
+ *     window that holds a non-finite element of A (as the definition does),
+ *     exactly those among the interior outputs; an output next to A's border
+ *     may also turn non-finite through a zero weight (0 * NaN).  Every
+ *     finite output is the definition's value.
  */
 #ifndef COVEST_H
 #define COVEST_H

@@ -455,8 +455,12 @@ __device__ void adj_interior_tile(const AdjArgs &aa, double2 *sm, int tile)
                 const float2 an = arow[b + v + RG - 1];
                 ring[(v + RG - 1) % RG] = make_double2(an.x, an.y);
                 const double2 wv = wrow[b + v];
+                // the padding lags dj >= 2Q-1 (zero weights) add nothing, and
+                // a non-finite A value there must not reach a product
+                if (b + v < nlag_c) {
 #pragma unroll
-                for (int u = 0; u < RG; ++u) cmla(acc[u], ring[(v + u) % RG], wv);
+                    for (int u = 0; u < RG; ++u) cmla(acc[u], ring[(v + u) % RG], wv);
+                }
             }
         }
     }

@@ -295,3 +295,39 @@ def test_adjoint_integer_exact(cv, tdev, oracle_mod, shape):
     else:
         ref = oracle_mod.adjoint_blas(A, G, P, Q, normalize=False)
     assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag)
+
+
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+@pytest.mark.parametrize("shape", [(64, 64, 8, 8), (90, 70, 12, 9), (140, 50, 16, 12), (300, 40, 20, 3)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_non_finite_input(cv, tdev, oracle_mod, shape, bad):
+    """Non-finite elements of A at a corner, on an edge and in the interior,
+    integer A and dR, FP64, no normalization.  The definition makes every
+    element of every window that holds such an element non-finite; the
+    kernels may also spread it to outputs whose zero weights meet it (0 * NaN).
+    What holds: every output the oracle makes non-finite is non-finite here
+    too, and every finite output equals the oracle's bit for bit (the
+    matrix-core interior zeroes its padded operands, so those stay finite)."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N * 3 + M + (1 if bad == "inf" else 0))
+    v = np.complex64(complex(np.nan, 0.0) if bad == "nan" else complex(0.0, np.inf))
+    for (r, c) in [(0, 0), (0, M // 2), (N // 2 + 1, M // 2 - 1)]:
+        A[r, c] = v
+    rng = np.random.default_rng(N + M + P)
+    PQ = P * Q
+    G = (rng.integers(-4, 5, (PQ, PQ)) + 1j * rng.integers(-4, 5, (PQ, PQ))).astype(np.complex128)
+    _note("adjoint non-finite input", shape, bad)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q, normalize=False)
+    torch.cuda.synchronize()
+    got = dA.cpu().numpy()
+    ref = oracle_mod.adjoint(A, G, P, Q, normalize=False)
+    bad_ref = ~np.isfinite(ref)
+    bad_gpu = ~np.isfinite(got)
+    assert bad_ref.any()
+    assert np.all(bad_gpu[bad_ref])
+    fin = ~bad_gpu
+    assert np.array_equal(got[fin], ref[fin])
+    # the interior's outputs are non-finite exactly where the definition's are
+    inner = (slice(P - 1, N - P + 1), slice(Q - 1, M - Q + 1))
+    assert np.array_equal(bad_gpu[inner], bad_ref[inner])
