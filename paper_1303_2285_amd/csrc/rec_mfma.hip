@@ -24,8 +24,9 @@
 // i.e. three MFMAs per 16 x 16 tile per k-group, into three accumulators that
 // are combined once per job.  Lag blocks of more than 4 tile rows keep the
 // four-product form (Re += yr*xr + yi*xi, Im += yr*xi + yi*(-xr)) in two
-// accumulators, which their registers allow; blocks of up to 4 rows run
-// their tile columns in passes small enough for three accumulators.
+// accumulators, which their registers allow; blocks of up to 4 rows (at
+// most 8 tiles) hold three accumulators per tile for all their tiles at once
+// (the 4 x 2 and 2 x 4 blocks spill a few values, outside the k-group loop).
 // Operands come straight from A (complex64) and are widened to FP64 in
 // registers; a product of two floats, and of a float and a sum or difference
 // of two floats, is exact in FP64 (the sum is, for parts within 2^28 of each
@@ -182,7 +183,7 @@ __device__ __forceinline__ void run_kgroups(int k_a, int k_b, v4d (&acc)[MT * NT
 // The planner sets job.kin, the k-groups that need no clamp: 0 for a line of
 // fewer than 4 positions past k0.
 template <int MT, int NT, int OR, int C>
-__device__ __forceinline__ void mfma_pass(const MJob &job, const Inst &in, double *red, int d2shift)
+__device__ __forceinline__ void mfma_pass(const MJob &job, const Inst &in, double *red)
 {
     constexpr int T = MT * NT;
     constexpr int span = 16 * NT - 1;      // lane lags d2 in [d2lo, d2lo + span]
@@ -198,7 +199,7 @@ __device__ __forceinline__ void mfma_pass(const MJob &job, const Inst &in, doubl
     const int nlines = OR ? in.M : in.N;
     const int npos = OR ? in.N : in.M;
     const int d1lo = OR ? 0 : -(in.P - 1);
-    const int d2lo = (OR ? -(in.P - 1) : 0) + d2shift;
+    const int d2lo = OR ? -(in.P - 1) : 0;
     // k-groups whose 4 positions all lie inside A (the planner counts them)
     const int kin = job.kin;
 
@@ -357,27 +358,13 @@ __device__ __forceinline__ void mfma_pass(const MJob &job, const Inst &in, doubl
                   [&](int t, int c, int r) { return at(0, t, c, r) + at(1, t, c, r); });
 }
 
-// A job in passes over its tile columns: lag blocks of at most 4 tile rows
-// take the three-product form with passes of NP columns (3 MT NP <= 12
-// accumulators, the registers of the four-product form's 8 tiles), larger
-// blocks the four-product form in one pass.  Passes restage their lines and
-// reload their first operands; they share nothing else.
-template <int MT, int NT>
-struct MfmaPasses {
-    static constexpr int C = MT <= 4 ? 3 : 2;
-    static constexpr int NP = C == 2 ? NT : (MT * NT <= 4 ? NT : (NT % 2 == 0 && MT * (NT / 2) <= 4) ? NT / 2 : 1);
-};
-
+// A job: lag blocks of at most 4 tile rows take the three-product form,
+// larger ones the four-product form; every tile of the block in one walk
+// over the job's lines.
 template <int MT, int NT, int OR>
 __device__ __forceinline__ void mfma_job(const MJob &job, const Inst &in, double *red)
 {
-    using PS = MfmaPasses<MT, NT>;
-    static_assert(NT % PS::NP == 0, "passes cover the tile columns");
-#pragma unroll 1
-    for (int n0 = 0; n0 < NT; n0 += PS::NP) {
-        if (n0 > 0) __syncthreads();   // the previous pass's LDS reads are done
-        mfma_pass<MT, PS::NP, OR, PS::C>(job, in, red, 16 * n0);
-    }
+    mfma_pass<MT, NT, OR, (MT <= 4 ? 3 : 2)>(job, in, red);
 }
 
 // One workgroup per job; orientation-1 jobs use the transposed tile shape
