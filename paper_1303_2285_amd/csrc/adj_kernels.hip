@@ -723,16 +723,15 @@ hipError_t launch_adjoint(const AdjArgs &aa_in, int n_lags, size_t lds_tables, i
     size_t lds = n_interior_blocks > 0 ? lds_interior : 0;
     if (n_frame_jobs > 0) lds = n_interior_blocks > 0 ? std::max(lds, frame_min) : (size_t)kAdjFrameLds;
     aa.frame_lds = (int)lds;
-    static bool attr = false;
-    if (!attr) {
+    static const hipError_t attr = [] {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_main),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_tables),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_tables),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return e;
+    }();
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(adj_tables, dim3(n_lags), dim3(256), lds_tables, s, aa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -776,14 +775,15 @@ hipError_t launch_adjoint_mfma(const AdjArgs &aa_in, int n_lags, size_t lds_tabl
 {
     AdjArgs aa = aa_in;
     aa.frame_lds = (int)lds_frame;
-    static hipError_t attr = hipSuccess;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // set once (a function-local static: thread-safe initialisation)
+    static const hipError_t attr = [] {
         const void *fns[] = {reinterpret_cast<const void *>(&adj_tables), reinterpret_cast<const void *>(&adj_frame_bnd)};
-        for (const void *f : fns)
-            if (attr == hipSuccess) attr = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+        for (const void *f : fns) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }();
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(adj_tables, dim3(n_lags), dim3(256), lds_tables, s, aa);
     hipError_t e = hipGetLastError();

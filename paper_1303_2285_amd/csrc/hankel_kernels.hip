@@ -553,13 +553,9 @@ __global__ void __launch_bounds__(256) hankel_reduce16(HankelArgs ha)
 template <int PREC, int WN>
 static hipError_t launch_main16_t(const HankelArgs &ha, int n, size_t lds, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&hankel_main16<PREC, WN>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&hankel_main16<PREC, WN>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((hankel_main16<PREC, WN>), dim3(n), dim3(kHThreads), lds, s, ha);
     return hipGetLastError();
 }
@@ -599,13 +595,9 @@ hipError_t launch_hankel_reduce16(const HankelArgs &ha, int n_tiles, hipStream_t
 template <int PREC>
 static hipError_t launch_main_t(const HankelArgs &ha, int n, size_t lds, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&hankel_main<PREC>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&hankel_main<PREC>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(hankel_main<PREC>, dim3(n), dim3(kHThreads), lds, s, ha);
     return hipGetLastError();
 }
