@@ -64,6 +64,25 @@ def test_matrix_engine_integer_bit_exact(cv, torch_dev, oracle_mod, shape):
     assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
 
 
+# one shape per lag-block size the engine instantiates that the list above
+# does not reach: MT x NT tiles = (1,1) .. (1,4), (2,3), (2,4), (3,1) (three
+# products per complex product, every tile in one walk) and (5,1) .. (8,1)
+# (four products)
+BLOCK_SHAPES = [(40, 40, 8, 16), (40, 80, 8, 32), (30, 100, 6, 48), (20, 130, 5, 64), (40, 100, 12, 40),
+                (40, 130, 10, 60), (60, 40, 20, 12), (80, 40, 36, 16), (90, 40, 44, 12), (110, 40, 52, 8),
+                (130, 40, 60, 8)]
+
+
+@pytest.mark.parametrize("shape", BLOCK_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_matrix_engine_every_block_bit_exact(cv, torch_dev, oracle_mod, shape):
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=7 * N + M + Q)
+    _note("matrix engine lag block", shape, cv.mfma_plan(N, M, P, Q)[0]["mt"], cv.mfma_plan(N, M, P, Q)[0]["nt"])
+    R = run(cv, torch_dev, A, P, Q, engine="matrix")
+    ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
+
+
 @pytest.mark.parametrize("shape", [(40, 36, 16, 16), (160, 150, 24, 31), (256, 256, 16, 16)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_matrix_engine_gaussian(cv, torch_dev, oracle_mod, shape):
