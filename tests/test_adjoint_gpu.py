@@ -331,3 +331,34 @@ def test_adjoint_non_finite_input(cv, tdev, oracle_mod, shape, bad):
     # the interior's outputs are non-finite exactly where the definition's are
     inner = (slice(P - 1, N - P + 1), slice(Q - 1, M - Q + 1))
     assert np.array_equal(bad_gpu[inner], bad_ref[inner])
+
+
+def _sweep_shapes(n=16, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        P, Q = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        N = int(rng.integers(P, 2 * P + 150))
+        M = int(rng.integers(Q, 2 * Q + 90))
+        if P * Q * P * Q * (N - P + 1) * (M - Q + 1) <= 4e8:   # the oracle's direct loops stay short
+            out.append((N, M, P, Q))
+    return out
+
+
+@pytest.mark.parametrize("shape", _sweep_shapes(), ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_sweep_integer_exact(cv, tdev, oracle_mod, shape):
+    """Seeded shapes with windows up to 16 x 16 (the matrix-core interior, its
+    span boundaries and ragged tiles, thin and empty interiors), integer A and
+    dR, FP64, no normalization: bit for bit against the oracle's adjoint."""
+    torch, dev = tdev
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=N * 7 + M * 3 + P + Q)
+    rng = np.random.default_rng(N * M + P * Q)
+    PQ = P * Q
+    G = (rng.integers(-4, 5, (PQ, PQ)) + 1j * rng.integers(-4, 5, (PQ, PQ))).astype(np.complex128)
+    _note("adjoint sweep", shape)
+    dA = cv.covest_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev), P, Q, normalize=False)
+    torch.cuda.synchronize()
+    got = dA.cpu().numpy()
+    ref = oracle_mod.adjoint(A, G, P, Q, normalize=False)
+    assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag)
