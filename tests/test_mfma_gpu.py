@@ -183,3 +183,28 @@ def test_matrix_engine_thin_inputs_bit_exact(cv, torch_dev, oracle_mod, shape, e
     R = run(cv, torch_dev, A, P, Q, engine=engine)
     ref = oracle_mod.forward(A, P, Q)
     assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
+
+
+def _sweep_shapes(n=20, seed=77):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        P, Q = int(rng.integers(1, 40)), int(rng.integers(4, 64))
+        N = int(rng.integers(2 * P - 1, 2 * P + 120))
+        M = int(rng.integers(2 * Q - 1, 2 * Q + 120))
+        mt, nt = (2 * P - 1 + 15) // 16, (Q + 15) // 16
+        if mt * nt <= 8 and (P * Q) ** 2 * (N - P + 1) * (M - Q + 1) <= 6e8:
+            out.append((N, M, P, Q))
+    return out
+
+
+@pytest.mark.parametrize("shape", _sweep_shapes(), ids=lambda s: "x".join(map(str, s)))
+def test_matrix_engine_sweep_bit_exact(cv, torch_dev, oracle_mod, shape):
+    """Seeded shapes over the engine's lag-block sizes (up to 8 tiles), ragged
+    lines and thin inputs, small-integer input: bit for bit against the oracle."""
+    N, M, P, Q = shape
+    A = synth.small_int(N, M, seed=3 * N + 5 * M + P)
+    _note("matrix engine sweep", shape)
+    R = run(cv, torch_dev, A, P, Q, engine="matrix")
+    ref = oracle_mod.forward(A, P, Q, threads=oracle_mod.max_threads())
+    assert np.array_equal(R.real, ref.real) and np.array_equal(R.imag, ref.imag)
